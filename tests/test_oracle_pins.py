@@ -1,0 +1,344 @@
+"""Pins of the FP64 oracle against things other than itself.
+
+Each test checks the oracle against a closed form, a brute-force
+contraction, a library routine used in a different way, or an invariant of
+the mathematics, chosen so that a dropped term, a wrong index or a
+transposed operand in the oracle fails at least one of them.
+"""
+
+import os
+
+import numpy as np
+import pytest
+from scipy.special import ellipk
+
+import oracle as O
+import oracle.ctm as OC
+from bruteforce import patch_bond_energy
+from synth import product_state_tensors, random_orthogonal, random_rotation2, site_tensors
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED])
+@pytest.mark.parametrize("chi", [1, 4])
+def test_neel_product_state_energy(method, chi):
+    """D = 1 Neel state: <S.S> = -1/4 on every bond, -1/2 per site."""
+    A = np.zeros((2, 1, 1, 1, 1)); A[0] = 1.0
+    B = np.zeros((2, 1, 1, 1, 1)); B[1] = 1.0
+    r = O.solve(A, B, chi, method, max_iters=3)
+    assert abs(r["e_site"] + 0.5) < 1e-14
+    for e in r["e_bond"]:
+        assert abs(e + 0.25) < 1e-14
+
+
+def _spin_expectation(psi):
+    sx = np.array([[0.0, 1.0], [1.0, 0.0]]) / 2
+    sz = np.array([[1.0, 0.0], [0.0, -1.0]]) / 2
+    n = psi @ psi
+    return np.array([psi @ sx @ psi / n, 0.0, psi @ sz @ psi / n])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_random_product_state_energy(seed):
+    """D = 1 product states: <S_i.S_j> = <S>_i . <S>_j (S^y vanishes for
+    real states)."""
+    A, B, pa, pb = product_state_tensors(2, seed)
+    exact = _spin_expectation(pa) @ _spin_expectation(pb)
+    for method in (O.STANDARD, O.REDUCED):
+        r = O.solve(A, B, 3, method, max_iters=2)
+        for e in r["e_bond"]:
+            assert abs(e - exact) < 1e-13
+        assert abs(r["e_site"] - 2 * exact) < 1e-13
+
+
+# ------------------------------------------------------------ brute force
+
+def _bf_all(A, B, h2, nL, nR, nU, nD):
+    ext = dict(left=1 + 2 * nL, right=1 + 2 * nR, up=1 + 2 * nU, down=1 + 2 * nD)
+    return [patch_bond_energy(A, B, h2, True, "h", **ext),
+            patch_bond_energy(A, B, h2, False, "h", **ext),
+            patch_bond_energy(A, B, h2, True, "v", **ext),
+            patch_bond_energy(A, B, h2, False, "v", **ext)]
+
+
+def _ctm_all(env, A, B, h2):
+    return [O.bond_energy(env, A, B, "a", h2, 0), O.bond_energy(env, A, B, "b", h2, 0),
+            O.bond_energy(env, A, B, "a", h2, 1), O.bond_energy(env, A, B, "b", h2, 1)]
+
+
+@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED])
+def test_untruncated_ctm_equals_bruteforce_patch(method):
+    """With identity isometries every move is an exact contraction: after
+    moves L / L,R,U,D the environment is the traced boundary of a finite
+    patch grown by two sites per move, contracted here column by column with
+    no environment tensors at all (init, rotation, absorption topology and
+    the energy networks are all pinned)."""
+    h2 = O.heisenberg_h2()
+    A, B = site_tensors(2, 2, 3)
+    env = O.init_env(A, B)
+    np.testing.assert_allclose(_ctm_all(env, A, B, h2), _bf_all(A, B, h2, 0, 0, 0, 0),
+                               rtol=0, atol=1e-12)
+    e1 = O.move(env, A, B, 0, 8, method, untruncated=True)
+    np.testing.assert_allclose(_ctm_all(e1, A, B, h2), _bf_all(A, B, h2, 1, 0, 0, 0),
+                               rtol=0, atol=1e-12)
+    e2 = O.move(env, A, B, 1, 8, method, untruncated=True)
+    np.testing.assert_allclose(_ctm_all(e2, A, B, h2), _bf_all(A, B, h2, 0, 0, 1, 0),
+                               rtol=0, atol=1e-12)
+    e4 = O.ctm_iteration(env, A, B, 8, method, untruncated=True)
+    np.testing.assert_allclose(_ctm_all(e4, A, B, h2), _bf_all(A, B, h2, 1, 1, 1, 1),
+                               rtol=0, atol=1e-12)
+
+
+def test_untruncated_bruteforce_D3():
+    h2 = O.heisenberg_h2()
+    A, B = site_tensors(2, 3, 4)
+    env = O.init_env(A, B)
+    np.testing.assert_allclose(_ctm_all(env, A, B, h2), _bf_all(A, B, h2, 0, 0, 0, 0),
+                               rtol=0, atol=1e-12)
+    for method in (O.STANDARD, O.REDUCED):
+        e1 = O.move(env, A, B, 2, 9, method, untruncated=True)
+        np.testing.assert_allclose(_ctm_all(e1, A, B, h2), _bf_all(A, B, h2, 0, 1, 0, 0),
+                                   rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------ Onsager
+
+def _onsager_nn(beta):
+    k = 2 * np.sinh(2 * beta) / np.cosh(2 * beta) ** 2
+    return 0.5 / np.tanh(2 * beta) * (1 + (2 / np.pi) * (2 * np.tanh(2 * beta) ** 2 - 1)
+                                      * ellipk(k * k))
+
+
+def _ising_peps(beta):
+    """A[s,l,u,r,d] = Q[s,l]Q[s,u]Q[s,r]Q[s,d], Q Q^T = exp(beta/2 s s'):
+    then <psi|psi> is the classical Ising partition function at beta and
+    <sz sz> on a bond is the nearest-neighbour correlation."""
+    W = np.array([[np.exp(beta / 2), np.exp(-beta / 2)], [np.exp(-beta / 2), np.exp(beta / 2)]])
+    w, U = np.linalg.eigh(W)
+    Q = U @ np.diag(np.sqrt(w)) @ U.T
+    return np.einsum("sl,su,sr,sd->slurd", Q, Q, Q, Q)
+
+
+def _golden_onsager():
+    vals = {}
+    with open(os.path.join(GOLDEN, "onsager_nn.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                b, v = line.split()
+                vals[float(b)] = float(v)
+    return vals
+
+
+def test_onsager_golden_values():
+    for beta, v in _golden_onsager().items():
+        assert abs(_onsager_nn(beta) - v) < 1e-11
+
+
+@pytest.mark.parametrize("beta", [0.3, 0.4])
+@pytest.mark.parametrize("method,boot", [(O.STANDARD, 1), (O.REDUCED, 3)])
+def test_onsager_nearest_neighbour(beta, method, boot):
+    """Converged truncated CTMRG (projectors and SVDs included) reproduces
+    Onsager's exact nearest-neighbour correlation.  The Ising legs span a
+    2-dim subspace of each D^2 bond, so the reduced move needs a few
+    standard iterations to reach full numerical rank before it takes over."""
+    A = _ising_peps(beta)
+    zz = np.kron(np.diag([1.0, -1.0]), np.diag([1.0, -1.0]))
+    r = O.solve(A, A, 24, method, max_iters=60, tol=1e-11, h2=zz, boot_iters=boot)
+    exact = _golden_onsager()[beta]
+    for e in r["e_bond"]:
+        assert abs(e - exact) < 1e-9
+
+
+# ------------------------------------------------------------ truncation
+
+def _mats():
+    rng = np.random.default_rng(7)
+    out = [rng.standard_normal((12, 12)), rng.standard_normal((20, 9)),
+           rng.standard_normal((7, 15))]
+    lo = rng.standard_normal((16, 3)) @ rng.standard_normal((3, 10))   # rank 3
+    out.append(lo)
+    # graded spectrum
+    Q1 = random_orthogonal(10, 1); Q2 = random_orthogonal(10, 2)
+    out.append(Q1 @ np.diag(10.0 ** -np.arange(10)) @ Q2)
+    return out
+
+
+@pytest.mark.parametrize("k", [1, 3, 5, 8])
+def test_truncate_eckart_young(k):
+    """||M - U U^T M||_F^2 = sum of discarded sigma^2 (eigenvalues of M M^T
+    from the symmetric eigensolver, not the SVD); U^T U = I on kept
+    columns; sign rule; zeroed columns below the cutoff."""
+    for M in _mats():
+        m, n = M.shape
+        U, S = O.truncate(M, k)
+        kk = min(k, m, n)
+        assert U.shape == (m, kk) and S.shape == (kk,)
+        lam = np.sort(np.clip(np.linalg.eigvalsh(M @ M.T), 0, None))[::-1]
+        keep = S > 0
+        R = M - U @ (U.T @ M)
+        discarded = lam[int(keep.sum()):].sum()
+        assert abs(np.sum(R * R) - discarded) <= 1e-10 * lam[0]
+        np.testing.assert_allclose(S[keep] ** 2, lam[:int(keep.sum())], rtol=1e-9, atol=1e-12 * lam[0])
+        G = U.T @ U
+        np.testing.assert_allclose(G, np.diag(keep.astype(float)), atol=1e-12)
+        for c in np.nonzero(keep)[0]:
+            a = np.abs(U[:, c])
+            i = np.nonzero(a >= (1 - OC.SIGN_TIE) * a.max())[0][0]
+            assert U[i, c] > 0
+        assert np.all(U[:, ~keep] == 0)
+
+
+def test_truncate_rank_deficient_cutoff():
+    rng = np.random.default_rng(3)
+    M = rng.standard_normal((16, 2)) @ rng.standard_normal((2, 16))
+    U, S = O.truncate(M, 6)
+    assert np.count_nonzero(S) == 2
+    assert np.all(U[:, 2:] == 0)
+    U0, S0 = O.truncate(np.zeros((4, 5)), 3)
+    assert U0.shape == (4, 3) and not U0.any() and not S0.any()
+
+
+def test_truncate_sign_tie_is_stable():
+    """Mirrored entries (the ket <-> bra symmetry of the standard move)
+    produce exact ties; the lowest tied row decides, whatever the rounding."""
+    v = np.array([0.0, 0.6, 0.2, -0.6, 0.1])
+    M = np.outer(v, [1.0, 2.0])
+    for eps in (0.0, 1e-15, -1e-15):
+        Mp = M.copy(); Mp[3, 0] *= (1 + eps)
+        U, _ = O.truncate(Mp, 1)
+        assert U[1, 0] > 0
+
+
+# ------------------------------------------------------------ invariances
+
+def _gauge(A, B, seed):
+    D = A.shape[1]
+    O1, O2, O3, O4 = [random_orthogonal(D, seed + i) for i in range(4)]
+    A2 = np.einsum("slurd,lL,uU,rR,dD->sLURD", A, O2, O3, O1, O4)
+    B2 = np.einsum("slurd,lL,uU,rR,dD->sLURD", B, O1, O4, O2, O3)
+    return A2, B2
+
+
+@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED])
+@pytest.mark.parametrize("D,chi,its", [(2, 8, 20), (3, 18, 3)])
+def test_bond_gauge_invariance(method, D, chi, its):
+    """An independent real orthogonal change of basis on each of the four
+    bond types leaves the state, hence every bond energy, unchanged; any
+    projector applied to the wrong bond or leg would break this."""
+    A, B = site_tensors(2, D, 1)
+    A2, B2 = _gauge(A, B, 10)
+    r1 = O.solve(A, B, chi, method, max_iters=its)
+    r2 = O.solve(A2, B2, chi, method, max_iters=its)
+    np.testing.assert_allclose(r1["e_bond"], r2["e_bond"], rtol=0, atol=1e-12)
+
+
+def test_broken_gauge_changes_energy():
+    A, B = site_tensors(2, 2, 1)
+    Q = random_orthogonal(2, 3)
+    A3 = np.einsum("slurd,rR->sluRd", A, Q)
+    e1 = O.solve(A, B, 8, O.REDUCED, max_iters=3)["e_site"]
+    e2 = O.solve(A3, B, 8, O.REDUCED, max_iters=3)["e_site"]
+    assert abs(e1 - e2) > 1e-3
+
+
+@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED])
+def test_spin_rotation_invariance(method):
+    """A real rotation of the physical index of A and B is a global SU(2)
+    rotation: S.S energies and the norm network (corner spectra) are
+    unchanged."""
+    A, B = site_tensors(2, 2, 2)
+    R = random_rotation2(9)
+    A2 = np.einsum("st,tlurd->slurd", R, A)
+    B2 = np.einsum("st,tlurd->slurd", R, B)
+    r1 = O.solve(A, B, 8, method, max_iters=6)
+    r2 = O.solve(A2, B2, 8, method, max_iters=6)
+    np.testing.assert_allclose(r1["e_bond"], r2["e_bond"], rtol=0, atol=1e-12)
+    s1, s2 = O.corner_spectra(r1["env"], 8), O.corner_spectra(r2["env"], 8)
+    for k in O.CORNERS:
+        np.testing.assert_allclose(s1[k], s2[k], rtol=0, atol=1e-9)
+
+
+def test_swap_sublattices():
+    """Exchanging A and B exchanges the a and b environments."""
+    A, B = site_tensors(2, 2, 5)
+    for method in (O.STANDARD, O.REDUCED):
+        r1 = O.solve(A, B, 8, method, max_iters=4)
+        r2 = O.solve(B, A, 8, method, max_iters=4)
+        e1, e2 = r1["e_bond"], r2["e_bond"]
+        np.testing.assert_allclose([e1[0], e1[1], e1[2], e1[3]], [e2[1], e2[0], e2[3], e2[2]],
+                                   rtol=0, atol=1e-12)
+        for key in O.ENV_KEYS:
+            other = key[:2] + ("b" if key[2] == "a" else "a")
+            np.testing.assert_allclose(r1["env"][key], r2["env"][other], rtol=0, atol=1e-9)
+
+
+def test_c4v_symmetric_state_has_equal_directions():
+    """A = B invariant under the 8 symmetries of the square: once converged
+    the four corners have the same spectrum (the rotation relabel and the
+    site transposes of every frame are pinned together)."""
+    A, _ = site_tensors(2, 2, 6)
+    perms = []
+    for r in range(4):
+        X = O.rotate_site(A, r)
+        perms.append(X)
+        perms.append(X.transpose(0, 3, 2, 1, 4))     # mirror l <-> r
+    S = sum(perms) / len(perms)
+    r = O.solve(S, S, 8, O.STANDARD, max_iters=60, tol=1e-12)
+    sp = O.corner_spectra(r["env"], 8)
+    for k in ("C2a", "C3a", "C4a", "C1b"):
+        np.testing.assert_allclose(sp[k], sp["C1a"], rtol=0, atol=1e-8)
+
+
+# ------------------------------------------------------------ reduced anchor
+
+def test_reduced_row_is_exact_without_truncation():
+    """If chi' is large enough that v_l, v_r truncate nothing, the
+    approximated row C'1 T'2 C'2 equals the reduced half-network
+    [C1 T2 C2; T1 z T3] contracted in one go (Appendix, Fig. A)."""
+    A, B = site_tensors(2, 2, 8)
+    env = O.solve(A, B, 8, O.STANDARD, max_iters=2)["env"]
+    sites = {"a": A, "b": B}
+    for z in "ab":
+        _, _, parts = OC.anchor_reduced(env, sites, z, 64, return_parts=True)
+        X = sites[z]
+        # one network, contracted by numpy's path optimiser in one call:
+        # C1[m,i] T1[j,k,l,m] T2[i,u,v,q] A[s,k,u,r,d] A[s,l,v,R,D] C2[q,n] T3[n,r,R,o]
+        exact = np.einsum("mi,jklm,iuvq,skurd,slvRD,qn,nrRo->jdDo",
+                          env[f"C1{z}"], env[f"T1{z}"], env[f"T2{z}"], X, X,
+                          env[f"C2{z}"], env[f"T3{z}"], optimize=True)
+        np.testing.assert_allclose(parts["Mp"], exact, rtol=0, atol=1e-12 * np.abs(exact).max())
+
+
+def test_sequential_isometries_reproduce_first_stage():
+    """With chi'' >= rank N, v2 spans range(N), so the composite
+    v = v1 v2 projects M' exactly as v1 alone does (Sec. IV)."""
+    A, B = site_tensors(2, 2, 9)
+    env = O.solve(A, B, 8, O.REDUCED, max_iters=3)["env"]
+    sites = {"a": A, "b": B}
+    for z in "ab":
+        v1, v2, parts = OC.anchor_reduced(env, sites, z, 8, return_parts=True)
+        Mp = parts["Mp"]
+        nj, D = Mp.shape[0], Mp.shape[1]
+        Mmat = Mp.reshape(nj * D * D, -1)
+        v = np.einsum("jdm,mDn->jdDn", v1, v2).reshape(nj * D * D, -1)
+        P1 = np.einsum("jdm,kem->jdke", v1, v1).reshape(nj * D, nj * D)
+        lhs = v @ (v.T @ Mmat)
+        rhs = np.einsum("ab,bDo->aDo", P1, Mp.reshape(nj * D, D, -1)).reshape(nj * D * D, -1)
+        np.testing.assert_allclose(lhs, rhs, atol=1e-12 * np.abs(Mmat).max())
+        np.testing.assert_allclose(v.T @ v, np.diag((np.abs(v).sum(0) > 0).astype(float)), atol=1e-12)
+
+
+@pytest.mark.parametrize("D,chis", [(2, (8, 32)), (3, (9, 27))])
+def test_reduced_approaches_standard_as_chi_grows(D, chis):
+    """Trend only (Sec. V: the methods agree for large chi); the finite-chi
+    gap itself is not pinned."""
+    A, B = site_tensors(2, D, 0)
+    gaps = []
+    for chi in chis:
+        es = O.solve(A, B, chi, O.STANDARD, max_iters=30, tol=1e-10)["e_site"]
+        er = O.solve(A, B, chi, O.REDUCED, max_iters=30, tol=1e-10)["e_site"]
+        gaps.append(abs(es - er))
+    assert gaps[1] < gaps[0] / 10
