@@ -1,0 +1,147 @@
+/* ctm.h -- corner-transfer renormalisation (CTMRG) environments of a
+ * two-site-unit-cell square-lattice iPEPS on one AMD MI355X (gfx950) GPU.
+ *
+ * Method: W. Lan and G. Evenbly, "Reduced Contraction Costs of
+ * Corner-Transfer Methods for PEPS", arXiv:2306.08212.
+ *   - problem statement (local tensors A, B of dimensions (d, D, D, D, D);
+ *     environment {C^i, T^i} of boundary dimension chi; left/right/up/down
+ *     moves repeated until converged): Sec. II, Figs. 1-2;
+ *   - standard isometries (SVD of the half-plaquette, cost chi^3 D^6):
+ *     Sec. II, Fig. 2(c);
+ *   - reduced environment and sequential ket-then-bra ("sequential-order")
+ *     isometries v^1, v^2, cost chi^3 D^3: Secs. III-IV, Figs. 3-4 and the
+ *     Appendix (helper isometries v_l, v_r);
+ *   - bond energy of the Heisenberg model: Sec. V, Eq. (1).
+ *
+ * Conventions (the paper's figures are not available; these are fixed here):
+ *   Site tensors are row-major double arrays A[s][l][u][r][d], d * D^4
+ *   values each; A sits on sublattice a, B on sublattice b (checkerboard).
+ *   The environment holds 16 tensors, index e = 8*kind + 2*(i-1) + z with
+ *   kind 0 = corner C^i, 1 = edge T^i, i = 1..4, z = 0 (a) or 1 (b):
+ *   C1, C2, C3, C4 are the up-left, up-right, down-right, down-left corners of
+ *   a z-site and T1, T2, T3, T4 the edges left of, above, right of and below
+ *   it.  Index order runs clockwise around the boundary: C^i[p][q] with p the
+ *   bond to T^i and q the bond to T^{i+1}; T^i[p][k][b][q] with p toward
+ *   C^{i-1}, q toward C^i and (k, b) the ket and bra legs into the site
+ *   (each of dimension D).  Bond dimensions start at D^2 (traced-boundary
+ *   initial environment) and grow to at most chi.
+ *
+ * Errors: every function returns a ctm_status (CTM_OK = 0); nothing throws
+ * across this interface.  All functions taking a solver enqueue work on the
+ * solver's stream and return without waiting unless stated otherwise.
+ */
+#ifndef CTM_H
+#define CTM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ctm_solver ctm_solver; /* opaque, owned by the library */
+
+enum ctm_status {
+  CTM_OK = 0,
+  CTM_EINVAL = 1,    /* bad argument (dimension < 1, NULL pointer, bad enum) */
+  CTM_ENOMEM = 2,    /* workspace smaller than ctm_workspace_size()         */
+  CTM_EHIP = 3,      /* a HIP runtime call failed                            */
+  CTM_ENUMERIC = 4,  /* a tensor norm was zero, NaN or Inf                   */
+  CTM_ENOTCONV = 5   /* ctm_converge reached max_iters; state stays valid    */
+};
+
+enum ctm_method {
+  CTM_STANDARD = 0,  /* standard isometries every move (Sec. II)             */
+  CTM_REDUCED = 1    /* sequential-order isometries (Secs. III-IV, App.)     */
+};
+
+enum ctm_precision {
+  CTM_FP64 = 0,      /* every contraction in FP64                            */
+  CTM_FP32 = 1,      /* absorption chains on FP32 MFMA; SVDs, norms, energy FP64 */
+  CTM_BF16 = 2       /* absorption chains on BF16 MFMA with FP32 accumulation */
+};
+
+enum ctm_dir { CTM_LEFT = 0, CTM_UP = 1, CTM_RIGHT = 2, CTM_DOWN = 3 };
+
+typedef struct {
+  int d;                 /* physical dimension (>= 2)                         */
+  int D;                 /* virtual bond dimension (>= 1)                     */
+  int chi;               /* boundary dimension (>= 1)                         */
+  int method;            /* enum ctm_method                                   */
+  int precision;         /* enum ctm_precision                                */
+  int boot_iters;        /* leading iterations that use standard isometries
+                            whatever the method (>= 0; 0 = only where the
+                            reduced move could not grow a bond, by shape)    */
+  double svd_cutoff;     /* relative singular-value cutoff tau (1e-14)        */
+  void *stream;          /* hipStream_t the solver is bound to; NULL = null stream */
+  void *workspace;       /* caller-owned device memory, >= ctm_workspace_size */
+  size_t workspace_bytes;
+} ctm_config;
+
+/* Exact peak device bytes one solver uses for cfg (all of it inside the
+ * caller's workspace; the library allocates no device memory of its own).
+ * Host-only; returns 0 for an invalid cfg. */
+size_t ctm_workspace_size(const ctm_config *cfg);
+
+/* Create a solver: copies A and B (host or device pointers, ptrs_on_device),
+ * builds the traced-boundary environment and normalises it.  *out receives
+ * the handle; free it with ctm_destroy.  Synchronises the stream once. */
+int ctm_init(const ctm_config *cfg, const double *A, const double *B, int ptrs_on_device,
+             ctm_solver **out);
+
+/* One directional move (two column insertions, Sec. II) in direction dir. */
+int ctm_move(ctm_solver *s, int dir);
+
+/* n full iterations (moves left, right, up, down) with no host round trip. */
+int ctm_iterate(ctm_solver *s, int n);
+
+/* Iterate until the normalised corner spectra change by less than tol
+ * (max abs over the 8 corners) or max_iters iterations; reads one scalar
+ * per iteration (synchronises).  iters_done/delta may be NULL. */
+int ctm_converge(ctm_solver *s, int max_iters, double tol, int *iters_done, double *delta);
+
+/* Bond energies <h> of the four bond types and the per-site energy
+ * e_site = (sum of e_bond) / 2.  h2 is a host d^2 x d^2 row-major operator
+ * h[(s1 s2)][(s1' s2')] acting on (left, right) or (top, bottom) sites, or
+ * NULL for S.S with S = sigma / 2.  e_bond order: horizontal (a left of b),
+ * horizontal (b left of a), vertical (a above b), vertical (b above a).
+ * Synchronises the stream. */
+int ctm_energy(ctm_solver *s, const double *h2, double *e_site, double e_bond[4]);
+
+/* Copy environment tensor e (0..15, see above) to host memory: writes its two
+ * boundary dimensions to *p, *q and, if host_out is not NULL and n is large
+ * enough (p*q for corners, p*D*D*q for edges), the values.  Synchronises. */
+int ctm_get_env(ctm_solver *s, int e, double *host_out, size_t n, int *p, int *q);
+
+/* Replace environment tensor e with host data of boundary dimensions (p, q),
+ * each at most max(chi, D^2) (warm start, resume). */
+int ctm_set_env(ctm_solver *s, int e, const double *host_in, int p, int q);
+
+/* Moves done so far. */
+int ctm_moves_done(const ctm_solver *s);
+
+/* Switch the precision of the absorption chains (enum ctm_precision) for the
+ * moves that follow; the environment is kept. */
+int ctm_set_precision(ctm_solver *s, int precision);
+
+/* Live kernel timing.  ctm_profile(s, 1) clears and starts recording a HIP
+ * event pair around every kernel launch of the solver (0 stops); both
+ * synchronise the stream.  ctm_profile_read returns, for one kernel class,
+ * the launches recorded, their summed duration in ms and their algorithmic
+ * flop and byte counts (synchronises).  Classes: 0 FP64 GEMM, 1 FP32 GEMM,
+ * 2 BF16 GEMM, 3 permute/cast, 4 Jacobi SVD round, 5 other SVD kernels,
+ * 6 norms and scaling, 7 device copies. */
+int ctm_profile(ctm_solver *s, int enable);
+int ctm_profile_read(ctm_solver *s, int cls, long long *launches, double *ms, double *flops,
+                     double *bytes);
+
+void ctm_destroy(ctm_solver *s);
+
+/* Static string for a status code (and the last HIP error of a solver, if any). */
+const char *ctm_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTM_H */

@@ -51,11 +51,11 @@ standard move is symmetric under ket <-> bra, so its singular vectors come
 in mirrored pairs of entries).
 
 Bootstrap.  The reduced sub-network has rank at most the dimension of the
-far-side boundary bond (T^3.q), so it cannot grow a bond.  The first
-boot_iters iterations (default 1) use the standard move; after that an
-insertion of the reduced method still falls back to the standard
-isometries whenever the reduced rule would leave a new bond smaller (by
-shape) than the standard rule would.
+far-side boundary bond (T^3.q), so it cannot grow a bond.  An insertion of
+the reduced method therefore uses the standard isometries whenever the
+reduced rule would leave a new bond smaller (by shape) than the standard
+rule would; optionally the first boot_iters iterations (default 0) use the
+standard move throughout.
 
 THIS MODULE IS TEST INFRASTRUCTURE; see the package docstring.
 """
@@ -136,12 +136,15 @@ def unframe_env(fenv, r):
 
 # ---------------------------------------------------------------- truncation
 
-def truncate(M, k, tau=TAU):
+def truncate(M, k, tau=None):
     """Top-k left singular vectors of the matrix M (Sec. II: the isometry is
     the truncated unitary of an SVD of a sub-network; Sec. IV: the same for
     v^1 and v^2).  Returns (U, S) with min(k, m, n) columns; columns with
-    sigma <= tau * sigma_0 are zeroed; each kept column is sign-fixed (the
-    lowest row within SIGN_TIE of the largest magnitude is positive)."""
+    sigma <= tau * sigma_0 are zeroed (tau defaults to the module's TAU,
+    read at call time); each kept column is sign-fixed (the lowest row within
+    SIGN_TIE of the largest magnitude is positive)."""
+    if tau is None:
+        tau = TAU
     m, n = M.shape
     kk = min(k, m, n)
     U, S, _ = np.linalg.svd(M, full_matrices=False)
@@ -428,21 +431,22 @@ def bond_energy(env, A, B, x, h2, r=0):
     sites = {"a": rotate_site(A, r), "b": rotate_site(B, r)}
     Ax, Ay = sites[x], sites[y]
     d = Ax.shape[0]
-    # left half -> HL[c, i, s1, r1, S1, R1]
+    # left half -> HL[c, s1, r1, i, S1, R1]; ket absorbed before T4 so no
+    # intermediate carries more than chi^2 D^4 d entries
     P = _c("ab,fkla->bfkl", f[f"C1{x}"], f[f"T1{x}"])
     P = _c("bfkl,hf->bklh", P, f[f"C4{x}"])
     P = _c("bklh,buUc->kluUch", P, f[f"T2{x}"])
-    P = _c("kluUch,idDh->kluUcidD", P, f[f"T4{x}"])
-    P = _c("kluUcidD,skurd->lUciDsr", P, Ax)
-    HL = _c("lUciDsr,SlURD->cisrSR", P, Ax)
-    # right half -> HR[c, i, t, r1, T, R1]
+    P = _c("kluUch,skurd->lhUcsrd", P, Ax)
+    P = _c("lhUcsrd,idDh->lUcsriD", P, f[f"T4{x}"])
+    HL = _c("lUcsriD,SlURD->csriSR", P, Ax)
+    # right half -> HR[c, t, r1, i, T, R1]
     Q = _c("eg,gkKj->ekKj", f[f"C2{y}"], f[f"T3{y}"])
     Q = _c("ekKj,jn->ekKn", Q, f[f"C3{y}"])
     Q = _c("ekKn,cuUe->kKncuU", Q, f[f"T2{y}"])
-    Q = _c("kKncuU,ndDi->kKcuUdDi", Q, f[f"T4{y}"])
-    Q = _c("kKcuUdDi,trukd->KcUDitr", Q, Ay)
-    HR = _c("KcUDitr,TRUKD->citrTR", Q, Ay)
-    rho = _c("cisrSR,citrTR->stST", HL, HR)      # [s1, s2, s1', s2']
+    Q = _c("kKncuU,trukd->KncUtrd", Q, Ay)
+    Q = _c("KncUtrd,ndDi->KcUtriD", Q, f[f"T4{y}"])
+    HR = _c("KcUtriD,TRUKD->ctriTR", Q, Ay)
+    rho = _c("csriSR,ctriTR->stST", HL, HR)      # [s1, s2, s1', s2']
     h4 = np.asarray(h2, dtype=np.float64).reshape(d, d, d, d)
     num = _c("stST,STst->", rho, h4)
     den = _c("stst->", rho)
@@ -461,7 +465,7 @@ def energy(env, A, B, h2=None):
 # ---------------------------------------------------------------- driver
 
 def solve(A, B, chi, method=REDUCED, max_iters=20, tol=0.0, h2=None, env=None,
-          boot_iters=1, callback=None):
+          boot_iters=0, callback=None):
     """Iterate CTM until the corner-spectrum change delta < tol (or
     max_iters).  The first boot_iters iterations use the standard move
     whatever the method.  Returns dict(env, iters, delta, e_site, e_bond,

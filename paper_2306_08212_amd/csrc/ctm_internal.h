@@ -1,0 +1,157 @@
+// Internal declarations of the corner-transfer library: device tensors,
+// the workspace arena, and the launch wrappers of every kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ctm {
+
+enum DType : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+inline size_t dtype_size(int dt) { return dt == F64 ? 8 : (dt == F32 ? 4 : 2); }
+
+constexpr int kMaxDims = 8;
+
+// A dense row-major tensor living in the workspace (or a dry-run stand-in).
+struct Tensor {
+  void* p = nullptr;
+  int dt = F64;
+  int nd = 0;
+  int64_t dims[kMaxDims] = {0};
+  int64_t numel() const {
+    int64_t n = 1;
+    for (int i = 0; i < nd; ++i) n *= dims[i];
+    return n;
+  }
+  size_t bytes() const { return (size_t)numel() * dtype_size(dt); }
+  double* d() const { return (double*)p; }
+  float* f() const { return (float*)p; }
+};
+
+Tensor make_view(void* p, int dt, std::initializer_list<int64_t> dims);
+Tensor make_view(void* p, int dt, const std::vector<int64_t>& dims);
+
+// Bump allocator over caller-owned device memory.  In dry-run mode it only
+// tracks the high-water mark; pointers are offsets from a fake base and no
+// kernel is launched.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t top = 0;
+  size_t peak = 0;
+  bool dry = false;
+  bool overflow = false;
+  void* alloc(size_t bytes);
+  size_t mark() const { return top; }
+  void release(size_t m) { top = m; }
+};
+
+// Kernel classes for live timing (HIP events around launches on the stream).
+enum KClass : int {
+  K_GEMM_F64 = 0, K_GEMM_F32, K_GEMM_BF16, K_PERMUTE, K_SVD_ROUND, K_SVD_OTHER, K_REDUCE,
+  K_COPY, K_NCLASS
+};
+
+struct Profiler {
+  struct Rec {
+    int cls;
+    double flops, bytes;
+    hipEvent_t e0, e1;
+  };
+  std::vector<Rec> recs;
+  long long n[K_NCLASS] = {0};
+  double ms[K_NCLASS] = {0}, flops[K_NCLASS] = {0}, bytes[K_NCLASS] = {0};
+  // resolve recorded events (the stream must have been synchronised)
+  void collect();
+  void clear();
+};
+
+struct Ctx {
+  hipStream_t stream = nullptr;
+  Profiler* prof = nullptr;
+  Arena arena;
+  bool dry = false;
+  hipError_t hip_err = hipSuccess;
+  int* dev_flags = nullptr;   // [0] numeric error, [1..] scratch counters
+  void check(hipError_t e) {
+    if (e != hipSuccess && hip_err == hipSuccess) hip_err = e;
+  }
+  void check_launch() { check(hipGetLastError()); }
+  Tensor alloc(int dt, std::initializer_list<int64_t> dims);
+  Tensor alloc(int dt, const std::vector<int64_t>& dims);
+};
+
+// Records one launch (or a short sequence) of class cls when profiling is on.
+struct ProfScope {
+  Ctx& c;
+  int cls;
+  double flops, bytes;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  ProfScope(Ctx& cx, int k, double f, double b) : c(cx), cls(k), flops(f), bytes(b) {
+    if (c.prof && !c.dry) {
+      c.check(hipEventCreate(&e0));
+      c.check(hipEventCreate(&e1));
+      c.check(hipEventRecord(e0, c.stream));
+    }
+  }
+  ~ProfScope() {
+    if (c.prof && !c.dry && e0) {
+      c.check(hipEventRecord(e1, c.stream));
+      c.prof->recs.push_back({cls, flops, bytes, e0, e1});
+    }
+  }
+};
+
+// ---------------------------------------------------------------- kernels
+
+// C[b] = alpha * op(A[b]) * op(B[b]) + beta * C[b], row-major; op(A) is m x k.
+// ta: A stored k x m (lda = row stride); tb: B stored n x k.
+// dtype: F64 (A,B,C double), F32 (A,B,C float), BF16 (A,B bf16, C float).
+void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A,
+          int64_t lda, int ta, const void* B, int64_t ldb, int tb, double beta,
+          void* C, int64_t ldc, int batch = 1, int64_t sA = 0, int64_t sB = 0,
+          int64_t sC = 0);
+
+// out = permute(in): out dims are in.dims[perm[i]]; dtype conversion allowed
+// (F64 <-> F32 <-> BF16) with an optional scale applied on the way.
+void permute(Ctx& c, const Tensor& in, const int* perm, Tensor& out,
+             double scale = 1.0);
+
+void fill(Ctx& c, void* p, int dt, int64_t n, double v);
+
+// Frobenius norm of x (F64) into *nrm (device); x *= 1/norm afterwards with
+// normalize(); a zero or non-finite norm raises the numeric error flag.
+void norm2(Ctx& c, const double* x, int64_t n, double* nrm);
+void scale_by_inv(Ctx& c, double* x, int64_t n, const double* nrm);
+
+// Truncated SVD of the row-major m x n F64 matrix M: U (m x kk, row-major)
+// holds the top kk = min(k, m, n) left singular vectors (cutoff tau relative
+// to sigma_0 zeroes columns; sign fixed), S (kk) the singular values.
+// M is left unchanged.
+void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U,
+          double* S);
+
+// Normalised singular values of a p x q corner, zero padded to chi.
+void corner_spectrum(Ctx& c, const double* C, int p, int q, int chi, double* out);
+
+// delta = max |a - b| over n entries, written to *out.
+void max_abs_diff(Ctx& c, const double* a, const double* b, int n, double* out);
+
+// Contract the reduced density matrix with h: out[0] = sum rho*h, out[1] = tr rho.
+void rho_energy(Ctx& c, const double* rho, const double* h4, int d, double* out);
+
+// General contraction helper: out(lo) = A(la) * B(lb), labels are single
+// characters; no label may appear in all three.  compute: F64/F32/BF16;
+// the result is written in out_dt.
+Tensor contract(Ctx& c, const Tensor& A, const char* la, const Tensor& B,
+                const char* lb, const char* lo, int compute, int out_dt);
+
+// Permute to a label order.
+Tensor relabel(Ctx& c, const Tensor& A, const char* la, const char* lo, int out_dt);
+
+}  // namespace ctm

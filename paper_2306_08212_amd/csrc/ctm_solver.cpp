@@ -1,0 +1,764 @@
+// Corner-transfer solver: schedule of one move and the C-ABI entry points.
+//
+// Every step runs in this library's kernels (GEMM, permute, SVD, norms); the
+// host only sequences launches on the solver's stream and tracks bond
+// dimensions, which are fixed by shapes alone (a truncation of an m x n
+// matrix to k keeps min(k, m, n) columns), so no host round trip is needed
+// inside a move.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+
+#include "../../include/ctm.h"
+#include "ctm_internal.h"
+
+using namespace ctm;
+
+struct ctm_solver {
+  Ctx ctx;
+  int d = 2, D = 1, chi = 1, method = CTM_REDUCED, precision = CTM_FP64, boot_iters = 1;
+  double tau = 1e-14;
+  int cap = 1;        // largest bond dimension any tensor can take
+  int moves = 0;
+  double* env[16] = {nullptr};
+  int pd[16] = {0}, qd[16] = {0};
+  double* site[2] = {nullptr, nullptr};
+  double* site_rot[4][2] = {};
+  void* sT1[4][2] = {};
+  void* sT2[4][2] = {};
+  double* spec[2] = {nullptr, nullptr};
+  int spec_cur = 0;
+  bool spec_valid = false;
+  double* scal = nullptr;    // device scalars
+  double* h4 = nullptr;      // device d^4 operator
+  size_t persist = 0;
+  Profiler prof;
+};
+
+namespace {
+
+constexpr int kC = 0, kT = 1;
+
+inline int env_index(int kind, int i, int z) { return 8 * kind + 2 * (i - 1) + z; }
+inline int stored_i(int i, int r) { return (i - 1 + r) % 4 + 1; }
+
+int cdt(const ctm_solver* s) {
+  return s->precision == CTM_FP64 ? F64 : (s->precision == CTM_FP32 ? F32 : BF16);
+}
+
+Tensor env_view(ctm_solver* s, int kind, int role_i, int z, int r) {
+  const int e = env_index(kind, stored_i(role_i, r), z);
+  if (kind == kC) return make_view(s->env[e], F64, {s->pd[e], s->qd[e]});
+  return make_view(s->env[e], F64, {s->pd[e], s->D, s->D, s->qd[e]});
+}
+
+Tensor site_view(ctm_solver* s, int r, int z) {
+  const int64_t d = s->d, D = s->D;
+  return make_view(s->site_rot[r][z], F64, {d, D, D, D, D});
+}
+
+// Copy t to dst and return the view at dst (device to device, stream ordered).
+Tensor keep(Ctx& c, const Tensor& t, void* dst) {
+  Tensor out = t;
+  out.p = dst;
+  if (!c.dry && t.p != dst && t.bytes() > 0) {
+    ProfScope ps(c, K_COPY, 0.0, 2.0 * t.bytes());
+    c.check(hipMemcpyAsync(dst, t.p, t.bytes(), hipMemcpyDeviceToDevice, c.stream));
+  }
+  return out;
+}
+
+Tensor reshape(const Tensor& t, std::initializer_list<int64_t> dims) {
+  Tensor o = make_view(t.p, t.dt, dims);
+  if (o.numel() != t.numel()) throw std::runtime_error("reshape: size mismatch");
+  return o;
+}
+
+// Truncated isometry of a row-major m x n F64 matrix: U (m x kk) at dst.
+Tensor isometry(ctm_solver* s, const Tensor& M, int64_t m, int64_t n, void* dst) {
+  Ctx& c = s->ctx;
+  const int kk = (int)std::min<int64_t>(s->chi, std::min(m, n));
+  const size_t mk = c.arena.mark();
+  double* S = (double*)c.arena.alloc(sizeof(double) * std::max(kk, 1));
+  tsvd(c, M.d(), (int)m, (int)n, s->chi, s->tau, (double*)dst, S);
+  c.arena.release(mk);
+  return make_view(dst, F64, {m, kk});
+}
+
+Tensor double_layer(ctm_solver* s, const Tensor& S) {
+  Tensor a = contract(s->ctx, S, "slurd", S, "sLURD", "lLuUrRdD", F64, F64);
+  return a;
+}
+
+// ---------------------------------------------------------------- anchors
+
+// Standard 4-index isometry v_z[j, kd, bd, nu] (Sec. II, Fig. 2(c)).
+Tensor anchor_standard(ctm_solver* s, int r, int z, void* dst) {
+  Ctx& c = s->ctx;
+  const int w = 1 - z;
+  const int64_t D = s->D;
+  Tensor C1 = env_view(s, kC, 1, z, r), T1 = env_view(s, kT, 1, z, r), T2 = env_view(s, kT, 2, z, r);
+  Tensor T2w = env_view(s, kT, 2, w, r), C2w = env_view(s, kC, 2, w, r), T3w = env_view(s, kT, 3, w, r);
+  const int64_t nj = T1.dims[0], nq = T2.dims[3], nj2 = T3w.dims[3];
+  const size_t mk = c.arena.mark();
+  Tensor az = double_layer(s, site_view(s, r, z));
+  Tensor X = contract(c, C1, "mn", T2, "nuvq", "muvq", F64, F64);
+  Tensor Y = contract(c, T1, "jklm", X, "muvq", "jkluvq", F64, F64);
+  Tensor Q1 = contract(c, Y, "jkluvq", az, "kluvrRdD", "jdDqrR", F64, F64);
+  Tensor aw = double_layer(s, site_view(s, r, w));
+  Tensor X2 = contract(c, T2w, "quvn", C2w, "nm", "quvm", F64, F64);
+  Tensor Y2 = contract(c, X2, "quvm", T3w, "mrRj", "quvrRj", F64, F64);
+  Tensor Q2 = contract(c, Y2, "quvrRj", aw, "lLuvrRdD", "qlLdDj", F64, F64);
+  const int64_t m = nj * D * D, k = nq * D * D, n = D * D * nj2;
+  Tensor M = c.alloc(F64, {m, n});
+  gemm(c, F64, (int)m, (int)n, (int)k, 1.0, Q1.p, k, 0, Q2.p, n, 0, 0.0, M.p, n);
+  Tensor U = isometry(s, M, m, n, dst);
+  c.arena.release(mk);
+  return make_view(dst, F64, {nj, D, D, U.dims[1]});
+}
+
+// Two-stage isometry of X[i,k,b,j] (bonded on (i,k,b)): v1 [i,k,mu], v2
+// [mu,b,nu], X''[nu,j] (Appendix, Fig. A(c)).  Outputs at the given buffers.
+void split_iso(ctm_solver* s, const Tensor& X, void* d1, void* d2, void* dxx, Tensor* v1o,
+               Tensor* v2o, Tensor* xxo) {
+  Ctx& c = s->ctx;
+  const int64_t ni = X.dims[0], D = X.dims[1], nj = X.dims[3];
+  const size_t mk = c.arena.mark();
+  Tensor v1 = isometry(s, X, ni * D, D * nj, d1);
+  const int64_t c1 = v1.dims[1];
+  v1 = reshape(v1, {ni, D, c1});
+  Tensor Xp = contract(c, v1, "ikm", X, "iklj", "mlj", F64, F64);
+  Tensor v2 = isometry(s, Xp, c1 * D, nj, d2);
+  const int64_t c2 = v2.dims[1];
+  v2 = reshape(v2, {c1, D, c2});
+  Tensor Xpp = contract(c, v2, "mln", Xp, "mlj", "nj", F64, F64);
+  *xxo = keep(c, Xpp, dxx);
+  c.arena.release(mk);
+  *v1o = v1;
+  *v2o = v2;
+}
+
+// Sequential ket-then-bra absorption of one site into an edge (Sec. IV,
+// Fig. 4(b)): T[p,k,b,q], site S[s, in, p-side, open, q-side] in the compute
+// type; the p-side bond takes (vp1, vp2), the q-side bond (vq1, vq2).
+// Returns out[nu_p, ko, bo, nu_q] in F64.
+Tensor chain(ctm_solver* s, const Tensor& T, const Tensor& S, const Tensor& vp1,
+             const Tensor& vp2, const Tensor& vq1, const Tensor& vq2) {
+  Ctx& c = s->ctx;
+  const int cp = cdt(s);
+  Tensor X1 = contract(c, T, "pkbq", vp1, "pim", "kbqim", cp, cp);
+  Tensor X2 = contract(c, X1, "kbqim", S, "skioj", "bqmsoj", cp, cp);
+  Tensor X3 = contract(c, X2, "bqmsoj", vq1, "qjn", "bmson", cp, cp);
+  Tensor X4 = contract(c, X3, "bmson", vp2, "mIv", "vIbson", cp, cp);
+  Tensor X5 = contract(c, X4, "vIbson", S, "sbIOJ", "vonOJ", cp, cp);
+  return contract(c, X5, "vonOJ", vq2, "nJw", "voOw", cp, F64);
+}
+
+struct SplitV {
+  Tensor v1, v2;
+};
+
+// Split isometries (v^1_z[j,kd,mu], v^2_z[mu,bd,nu]) from the reduced
+// half-network [C1 T2 C2; T1 z T3] (Secs. III-IV, Figs. 3-4, Appendix).
+SplitV anchor_reduced(ctm_solver* s, int r, int z, void* d1, void* d2) {
+  Ctx& c = s->ctx;
+  const int64_t D = s->D, cap = s->cap, chi = s->chi;
+  Tensor C1 = env_view(s, kC, 1, z, r), T1 = env_view(s, kT, 1, z, r), T2 = env_view(s, kT, 2, z, r);
+  Tensor C2 = env_view(s, kC, 2, z, r), T3 = env_view(s, kT, 3, z, r);
+  const int64_t nj = T1.dims[0], nj2 = T3.dims[3];
+  const size_t mk = c.arena.mark();
+  // buffers for the helper isometries and the compressed corners
+  void* bl1 = c.arena.alloc(sizeof(double) * cap * D * chi);
+  void* bl2 = c.arena.alloc(sizeof(double) * chi * D * chi);
+  void* br1 = c.arena.alloc(sizeof(double) * cap * D * chi);
+  void* br2 = c.arena.alloc(sizeof(double) * chi * D * chi);
+  void* bc1 = c.arena.alloc(sizeof(double) * chi * cap);
+  void* bc2 = c.arena.alloc(sizeof(double) * chi * cap);
+  void* btp = c.arena.alloc(sizeof(double) * chi * D * D * chi);
+  Tensor vl1, vl2, Cp1, vr1, vr2, Cp2;
+  {
+    const size_t m2 = c.arena.mark();
+    Tensor L = contract(c, C1, "mi", T1, "jklm", "iklj", F64, F64);
+    split_iso(s, L, bl1, bl2, bc1, &vl1, &vl2, &Cp1);
+    c.arena.release(m2);
+  }
+  {
+    const size_t m2 = c.arena.mark();
+    Tensor R = contract(c, C2, "im", T3, "mklj", "iklj", F64, F64);
+    split_iso(s, R, br1, br2, bc2, &vr1, &vr2, &Cp2);
+    c.arena.release(m2);
+  }
+  Tensor Tp2;
+  {
+    const size_t m2 = c.arena.mark();
+    const int cp = cdt(s);
+    Tensor S = make_view(s->sT2[r][z], cp, {s->d, D, D, D, D});
+    Tensor t = chain(s, T2, S, vl1, vl2, vr1, vr2);
+    Tp2 = keep(c, t, btp);
+    c.arena.release(m2);
+  }
+  Tensor Mp = contract(c, Cp1, "nj", Tp2, "ndDo", "jdDo", F64, F64);
+  Mp = contract(c, Mp, "jdDo", Cp2, "ok", "jdDk", F64, F64);
+  Tensor v1 = isometry(s, Mp, nj * D, D * nj2, d1);
+  const int64_t c1 = v1.dims[1];
+  v1 = reshape(v1, {nj, D, c1});
+  Tensor N = contract(c, v1, "jdm", Mp, "jdDk", "mDk", F64, F64);
+  Tensor v2 = isometry(s, N, c1 * D, nj2, d2);
+  const int64_t c2 = v2.dims[1];
+  v2 = reshape(v2, {c1, D, c2});
+  c.arena.release(mk);
+  return SplitV{v1, v2};
+}
+
+bool insertion_standard(const ctm_solver* s, int r) {
+  if (s->method == CTM_STANDARD) return true;
+  if (s->moves / 4 < s->boot_iters) return true;
+  const int64_t D = s->D, chi = s->chi;
+  for (int z = 0; z < 2; ++z) {
+    const int64_t nj = s->pd[env_index(kT, stored_i(1, r), z)];
+    const int64_t nj2 = s->qd[env_index(kT, stored_i(3, r), z)];
+    const int64_t sd = std::min({chi, nj * D * D, D * D * nj2});
+    const int64_t c1 = std::min({chi, nj * D, D * nj2});
+    const int64_t rd = std::min({chi, c1 * D, nj2});
+    if (rd < sd) return true;
+  }
+  return false;
+}
+
+void store_env(ctm_solver* s, int e, const Tensor& t) {
+  Ctx& c = s->ctx;
+  double* nrm = s->scal + e;   // one scalar slot per tensor
+  norm2(c, t.d(), t.numel(), nrm);
+  keep(c, t, s->env[e]);
+  scale_by_inv(c, s->env[e], t.numel(), nrm);
+  s->pd[e] = (int)t.dims[0];
+  s->qd[e] = (int)t.dims[t.nd - 1];
+}
+
+// Insert one column into the left environment (frame r) and truncate.
+void insert_column(ctm_solver* s, int r) {
+  Ctx& c = s->ctx;
+  const int64_t D = s->D, cap = s->cap, chi = s->chi;
+  const bool stdm = insertion_standard(s, r);
+  const size_t mk = c.arena.mark();
+  // anchors
+  Tensor V4[2];
+  SplitV VS[2];
+  for (int z = 0; z < 2; ++z) {
+    if (stdm) {
+      void* dv = c.arena.alloc(sizeof(double) * cap * D * D * chi);
+      V4[z] = anchor_standard(s, r, z, dv);
+    } else {
+      void* d1 = c.arena.alloc(sizeof(double) * cap * D * chi);
+      void* d2 = c.arena.alloc(sizeof(double) * chi * D * chi);
+      VS[z] = anchor_reduced(s, r, z, d1, d2);
+    }
+  }
+  // new tensors, staged until all six are done
+  Tensor nC1[2], nT1[2], nC4[2];
+  const int cp = cdt(s);
+  for (int x = 0; x < 2; ++x) {
+    const int y = 1 - x;
+    Tensor C1x = env_view(s, kC, 1, x, r), T2x = env_view(s, kT, 2, x, r);
+    Tensor T1x = env_view(s, kT, 1, x, r);
+    Tensor C4x = env_view(s, kC, 4, x, r), T4x = env_view(s, kT, 4, x, r);
+    void* bC1 = c.arena.alloc(sizeof(double) * cap * cap);
+    void* bT1 = c.arena.alloc(sizeof(double) * cap * D * D * cap);
+    void* bC4 = c.arena.alloc(sizeof(double) * cap * cap);
+    {
+      const size_t m2 = c.arena.mark();
+      Tensor G = contract(c, C1x, "jm", T2x, "mubq", "jubq", F64, F64);
+      Tensor t;
+      if (stdm) {
+        t = contract(c, G, "jubq", V4[y], "jubn", "nq", F64, F64);
+      } else {
+        Tensor G1 = contract(c, G, "jubq", VS[y].v1, "jum", "mbq", F64, F64);
+        t = contract(c, G1, "mbq", VS[y].v2, "mbn", "nq", F64, F64);
+      }
+      nC1[y] = keep(c, t, bC1);
+      c.arena.release(m2);
+    }
+    {
+      const size_t m2 = c.arena.mark();
+      Tensor t;
+      if (stdm) {
+        Tensor a = double_layer(s, site_view(s, r, x));
+        Tensor Z = contract(c, T1x, "pklq", V4[y], "quvn", "pkluvn", F64, F64);
+        Z = contract(c, Z, "pkluvn", a, "kluvrRdD", "pnrRdD", F64, F64);
+        t = contract(c, Z, "pnrRdD", V4[x], "pdDm", "mrRn", F64, F64);
+      } else {
+        Tensor S = make_view(s->sT1[r][x], cp, {s->d, D, D, D, D});
+        t = chain(s, T1x, S, VS[x].v1, VS[x].v2, VS[y].v1, VS[y].v2);
+      }
+      nT1[y] = keep(c, t, bT1);
+      c.arena.release(m2);
+    }
+    {
+      const size_t m2 = c.arena.mark();
+      Tensor G4 = contract(c, C4x, "mj", T4x, "pkbm", "jkbp", F64, F64);
+      Tensor t;
+      if (stdm) {
+        t = contract(c, G4, "jkbp", V4[x], "jkbn", "pn", F64, F64);
+      } else {
+        Tensor G5 = contract(c, G4, "jkbp", VS[x].v1, "jkm", "mbp", F64, F64);
+        t = contract(c, G5, "mbp", VS[x].v2, "mbn", "pn", F64, F64);
+      }
+      nC4[y] = keep(c, t, bC4);
+      c.arena.release(m2);
+    }
+  }
+  for (int y = 0; y < 2; ++y) {
+    store_env(s, env_index(kC, stored_i(1, r), y), nC1[y]);
+    store_env(s, env_index(kT, stored_i(1, r), y), nT1[y]);
+    store_env(s, env_index(kC, stored_i(4, r), y), nC4[y]);
+  }
+  c.arena.release(mk);
+}
+
+void do_move(ctm_solver* s, int r) {
+  insert_column(s, r);
+  insert_column(s, r);
+  s->moves++;
+}
+
+void do_iteration(ctm_solver* s) {
+  static const int order[4] = {CTM_LEFT, CTM_RIGHT, CTM_UP, CTM_DOWN};
+  for (int i = 0; i < 4; ++i) do_move(s, order[i]);
+}
+
+// normalised corner spectra of the 8 corners into spec[cur]
+void corner_spectra(ctm_solver* s) {
+  Ctx& c = s->ctx;
+  double* out = s->spec[s->spec_cur];
+  for (int z = 0; z < 2; ++z)
+    for (int i = 1; i <= 4; ++i) {
+      const int e = env_index(kC, i, z);
+      corner_spectrum(c, s->env[e], s->pd[e], s->qd[e], s->chi, out + (size_t)(i - 1 + 4 * z) * s->chi);
+    }
+}
+
+// Half of the bond network on the side of site x (frame r):
+// H[s, c, r1, i, S, R1] with c / i the bonds to T2 / T4 of the other half,
+// r1 / R1 the ket / bra legs toward the other site, s / S the physical
+// indices.  The ket site is absorbed one physical slice at a time, so no
+// intermediate exceeds chi^2 D^4 entries.
+Tensor half_network(ctm_solver* s, int x, int r, void* dst) {
+  Ctx& c = s->ctx;
+  const int64_t d = s->d, D = s->D;
+  const int64_t D4 = D * D * D * D;
+  Tensor C1 = env_view(s, kC, 1, x, r), T1 = env_view(s, kT, 1, x, r), C4 = env_view(s, kC, 4, x, r);
+  Tensor T2 = env_view(s, kT, 2, x, r), T4 = env_view(s, kT, 4, x, r);
+  const int64_t nc = T2.dims[3], ni = T4.dims[0];
+  Tensor H = make_view(dst, F64, {d, nc, D, ni, d, D});
+  const size_t mk = c.arena.mark();
+  Tensor L = contract(c, C1, "ab", T1, "fkla", "bfkl", F64, F64);
+  L = contract(c, L, "bfkl", C4, "hf", "bklh", F64, F64);
+  Tensor P2 = contract(c, L, "bklh", T2, "buUc", "klhuUc", F64, F64);
+  Tensor P2p = relabel(c, P2, "klhuUc", "lhUcku", F64);
+  Tensor Ax = site_view(s, r, x);
+  for (int64_t sl = 0; sl < d; ++sl) {
+    const size_t m2 = c.arena.mark();
+    Tensor As = make_view((double*)Ax.p + sl * D4, F64, {D, D, D, D});
+    Tensor P3 = contract(c, P2p, "lhUcku", As, "kurd", "lhUcrd", F64, F64);
+    Tensor P4 = contract(c, P3, "lhUcrd", T4, "idDh", "lUcriD", F64, F64);
+    Tensor Hs = contract(c, P4, "lUcriD", Ax, "SlURD", "criSR", F64, F64);
+    keep(c, Hs, (double*)dst + sl * (nc * D * ni * d * D));
+    c.arena.release(m2);
+  }
+  c.arena.release(mk);
+  return H;
+}
+
+// <h> numerator and trace for the bond (x, right neighbour) in frame r -> out[0..1]
+void bond_energy(ctm_solver* s, int x, int r, double* out) {
+  Ctx& c = s->ctx;
+  const int y = 1 - x;
+  const int64_t d = s->d, D = s->D;
+  const size_t mk = c.arena.mark();
+  // left half: site x in frame r; right half: site y seen from the mirrored
+  // frame r + 2, where its environment C3, T4, C2, T3, T2 plays C1, T2, C4,
+  // T1, T4 and the other site is on its left
+  const int rm = (r + 2) % 4;
+  const int64_t ncL = env_view(s, kT, 2, x, r).dims[3], niL = env_view(s, kT, 4, x, r).dims[0];
+  const int64_t ncR = env_view(s, kT, 2, y, rm).dims[3], niR = env_view(s, kT, 4, y, rm).dims[0];
+  void* bl = c.arena.alloc(sizeof(double) * d * ncL * D * niL * d * D);
+  void* br = c.arena.alloc(sizeof(double) * d * ncR * D * niR * d * D);
+  Tensor HL = half_network(s, x, r, bl);
+  Tensor HR = half_network(s, y, rm, br);
+  // HL[s, c, r1, i, S, R1] with c -> T2_y.p, i -> T4_y.q; in the mirrored
+  // frame the right half's T2-bond index is the T4_y.q bond of frame r and
+  // its T4-bond index the T2_y.p bond: HR[t, i, r1, c, T, R1]
+  Tensor rho = contract(c, HL, "scriSR", HR, "tircTR", "stST", F64, F64);
+  rho_energy(c, rho.d(), s->h4, s->d, out);
+  c.arena.release(mk);
+}
+
+// site layouts used by the absorption chains, in the compute type:
+// S[s, in, p-side, open, q-side] for the T1 chain and the T2 chain
+void rebuild_chain_sites(ctm_solver* s) {
+  Ctx& c = s->ctx;
+  const int64_t d = s->d, D = s->D;
+  const int cp = cdt(s);
+  for (int r = 0; r < 4; ++r)
+    for (int z = 0; z < 2; ++z) {
+      Tensor rot = make_view(s->site_rot[r][z], F64, {d, D, D, D, D});
+      const int p1[5] = {0, 1, 4, 3, 2}, p2[5] = {0, 2, 1, 4, 3};
+      Tensor o1 = make_view(s->sT1[r][z], cp, {d, D, D, D, D});
+      Tensor o2 = make_view(s->sT2[r][z], cp, {d, D, D, D, D});
+      permute(c, rot, p1, o1);
+      permute(c, rot, p2, o2);
+    }
+}
+
+void perm_rot(int r, int* p) {
+  // r quarter turns of (s,l,u,r,d) -> (s,u,r,d,l)
+  int cur[5] = {0, 1, 2, 3, 4};
+  const int one[5] = {0, 2, 3, 4, 1};
+  for (int t = 0; t < r; ++t) {
+    int nxt[5];
+    for (int i = 0; i < 5; ++i) nxt[i] = cur[one[i]];
+    std::memcpy(cur, nxt, sizeof(cur));
+  }
+  std::memcpy(p, cur, sizeof(cur));
+}
+
+// layout: persistent buffers, then sites and the traced-boundary environment
+void setup(ctm_solver* s, const double* A, const double* B, int on_device) {
+  Ctx& c = s->ctx;
+  const int64_t d = s->d, D = s->D, cap = s->cap, chi = s->chi;
+  for (int e = 0; e < 16; ++e) {
+    const size_t n = (e < 8) ? (size_t)cap * cap : (size_t)cap * D * D * cap;
+    s->env[e] = (double*)c.arena.alloc(n * sizeof(double));
+  }
+  const size_t ns = (size_t)(d * D * D * D * D);
+  for (int z = 0; z < 2; ++z) s->site[z] = (double*)c.arena.alloc(ns * sizeof(double));
+  for (int r = 0; r < 4; ++r)
+    for (int z = 0; z < 2; ++z) {
+      s->site_rot[r][z] = (double*)c.arena.alloc(ns * sizeof(double));
+      s->sT1[r][z] = c.arena.alloc(ns * sizeof(double));
+      s->sT2[r][z] = c.arena.alloc(ns * sizeof(double));
+    }
+  s->spec[0] = (double*)c.arena.alloc(8 * chi * sizeof(double));
+  s->spec[1] = (double*)c.arena.alloc(8 * chi * sizeof(double));
+  s->scal = (double*)c.arena.alloc(64 * sizeof(double));
+  s->h4 = (double*)c.arena.alloc(d * d * d * d * sizeof(double));
+  c.dev_flags = (int*)c.arena.alloc(16 * sizeof(int));
+  s->persist = c.arena.mark();
+  if (c.arena.overflow) return;
+  if (!c.dry) {
+    const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    c.check(hipMemcpyAsync(s->site[0], A, ns * sizeof(double), kind, c.stream));
+    c.check(hipMemcpyAsync(s->site[1], B, ns * sizeof(double), kind, c.stream));
+    fill(c, c.dev_flags, F32, 16, 0.0);   // 16 ints, zero bit pattern
+  }
+  for (int r = 0; r < 4; ++r)
+    for (int z = 0; z < 2; ++z) {
+      int p[5];
+      perm_rot(r, p);
+      Tensor in = make_view(s->site[z], F64, {d, D, D, D, D});
+      Tensor out = make_view(s->site_rot[r][z], F64, {d, D, D, D, D});
+      permute(c, in, p, out);
+    }
+  rebuild_chain_sites(s);
+  // traced-boundary environment (frame 0)
+  const int64_t D2 = D * D;
+  for (int z = 0; z < 2; ++z) {
+    Tensor X = site_view(s, 0, z), Y = site_view(s, 0, 1 - z);
+    const size_t mk = c.arena.mark();
+    struct Spec { int kind, i; const Tensor* t; const char* lb; const char* lo; };
+    const Spec sp[8] = {
+        {kC, 1, &X, "sluRD", "dDrR"},   {kC, 2, &X, "sLurD", "lLdD"},
+        {kC, 3, &X, "sLUrd", "uUlL"},   {kC, 4, &X, "slURd", "rRuU"},
+        {kT, 1, &Y, "slURD", "dDrRuU"}, {kT, 2, &Y, "sLuRD", "lLdDrR"},
+        {kT, 3, &Y, "sLUrD", "uUlLdD"}, {kT, 4, &Y, "sLURd", "rRuUlL"}};
+    for (const Spec& q : sp) {
+      const size_t m2 = c.arena.mark();
+      Tensor t = contract(c, *q.t, "slurd", *q.t, q.lb, q.lo, F64, F64);
+      Tensor v = q.kind == kC ? reshape(t, {D2, D2}) : reshape(t, {D2, D, D, D2});
+      store_env(s, env_index(q.kind, q.i, z), v);
+      c.arena.release(m2);
+    }
+    c.arena.release(mk);
+  }
+}
+
+int status_from(ctm_solver* s) {
+  if (s->ctx.arena.overflow) return CTM_ENOMEM;
+  if (s->ctx.hip_err != hipSuccess) return CTM_EHIP;
+  return CTM_OK;
+}
+
+bool valid_cfg(const ctm_config* cfg) {
+  if (!cfg) return false;
+  if (cfg->d < 2 || cfg->D < 1 || cfg->chi < 1) return false;
+  if (cfg->method != CTM_STANDARD && cfg->method != CTM_REDUCED) return false;
+  if (cfg->precision < CTM_FP64 || cfg->precision > CTM_BF16) return false;
+  if (cfg->boot_iters < 0) return false;
+  if (!(cfg->svd_cutoff >= 0.0) || cfg->svd_cutoff >= 1.0) return false;
+  // every dimension product must stay well inside 32-bit GEMM sizes
+  const double cap = std::max<double>(cfg->chi, (double)cfg->D * cfg->D);
+  if (cap * cfg->D * cfg->D * cfg->D * cfg->d > 2.0e9) return false;
+  return true;
+}
+
+void fill_from_cfg(ctm_solver* s, const ctm_config* cfg) {
+  s->d = cfg->d;
+  s->D = cfg->D;
+  s->chi = cfg->chi;
+  s->method = cfg->method;
+  s->precision = cfg->precision;
+  s->boot_iters = cfg->boot_iters;
+  s->tau = cfg->svd_cutoff;
+  s->cap = std::max(cfg->chi, cfg->D * cfg->D);
+  s->ctx.stream = (hipStream_t)cfg->stream;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+size_t ctm_workspace_size(const ctm_config* cfg) {
+  if (!valid_cfg(cfg)) return 0;
+  try {
+    ctm_solver s;
+    fill_from_cfg(&s, cfg);
+    s.ctx.dry = true;
+    s.ctx.arena.dry = true;
+    setup(&s, nullptr, nullptr, 0);
+    // shapes settle after the first iteration; two more cover the steady state
+    const int iters = std::max(1, s.boot_iters) + 2;
+    const bool dbg = std::getenv("CTM_DEBUG_MEM") != nullptr;
+    for (int it = 0; it < iters; ++it) {
+      for (int mv : {CTM_LEFT, CTM_RIGHT, CTM_UP, CTM_DOWN}) {
+        const bool stdm = insertion_standard(&s, mv);
+        do_move(&s, mv);
+        if (dbg) std::fprintf(stderr, "iter %d move %d std %d peak %.1f MB\n", it, mv, (int)stdm, s.ctx.arena.peak / 1e6);
+      }
+    }
+    corner_spectra(&s);
+    if (dbg) std::fprintf(stderr, "spectra peak %.1f MB\n", s.ctx.arena.peak / 1e6);
+    for (int k = 0; k < 4; ++k) bond_energy(&s, k & 1, k >> 1, s.scal);
+    if (dbg) std::fprintf(stderr, "energy peak %.1f MB\n", s.ctx.arena.peak / 1e6);
+    return s.ctx.arena.peak + 4096;
+  } catch (...) {
+    return 0;
+  }
+}
+
+int ctm_init(const ctm_config* cfg, const double* A, const double* B, int ptrs_on_device,
+             ctm_solver** out) {
+  if (!out) return CTM_EINVAL;
+  *out = nullptr;
+  if (!valid_cfg(cfg) || !A || !B || !cfg->workspace) return CTM_EINVAL;
+  const size_t need = ctm_workspace_size(cfg);
+  if (need == 0) return CTM_EINVAL;
+  if (cfg->workspace_bytes < need) return CTM_ENOMEM;
+  ctm_solver* s = new (std::nothrow) ctm_solver();
+  if (!s) return CTM_ENOMEM;
+  try {
+    fill_from_cfg(s, cfg);
+    s->ctx.arena.base = (char*)cfg->workspace;
+    s->ctx.arena.cap = cfg->workspace_bytes;
+    setup(s, A, B, ptrs_on_device);
+    s->ctx.check(hipStreamSynchronize(s->ctx.stream));
+    int st = status_from(s);
+    if (st == CTM_OK) {
+      int flag = 0;
+      s->ctx.check(hipMemcpy(&flag, s->ctx.dev_flags, sizeof(int), hipMemcpyDeviceToHost));
+      if (flag) st = CTM_ENUMERIC;
+      st = st == CTM_OK ? status_from(s) : st;
+    }
+    if (st != CTM_OK) {
+      delete s;
+      return st;
+    }
+  } catch (...) {
+    delete s;
+    return CTM_EINVAL;
+  }
+  *out = s;
+  return CTM_OK;
+}
+
+int ctm_move(ctm_solver* s, int dir) {
+  if (!s || dir < 0 || dir > 3) return CTM_EINVAL;
+  try {
+    do_move(s, dir);
+  } catch (...) {
+    return CTM_EINVAL;
+  }
+  s->spec_valid = false;
+  return status_from(s);
+}
+
+int ctm_iterate(ctm_solver* s, int n) {
+  if (!s || n < 0) return CTM_EINVAL;
+  try {
+    for (int i = 0; i < n; ++i) do_iteration(s);
+  } catch (...) {
+    return CTM_EINVAL;
+  }
+  s->spec_valid = false;
+  return status_from(s);
+}
+
+int ctm_converge(ctm_solver* s, int max_iters, double tol, int* iters_done, double* delta) {
+  if (!s || max_iters < 0) return CTM_EINVAL;
+  Ctx& c = s->ctx;
+  double dl = INFINITY;
+  int it = 0;
+  try {
+    if (!s->spec_valid) {
+      corner_spectra(s);
+      s->spec_valid = true;
+    }
+    for (it = 0; it < max_iters;) {
+      do_iteration(s);
+      ++it;
+      s->spec_cur ^= 1;
+      corner_spectra(s);
+      max_abs_diff(c, s->spec[s->spec_cur], s->spec[s->spec_cur ^ 1], 8 * s->chi, s->scal + 32);
+      int flag = 0;
+      c.check(hipMemcpyAsync(&dl, s->scal + 32, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+      c.check(hipMemcpyAsync(&flag, c.dev_flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+      c.check(hipStreamSynchronize(c.stream));
+      if (status_from(s) != CTM_OK) break;
+      if (flag) {
+        if (iters_done) *iters_done = it;
+        if (delta) *delta = dl;
+        return CTM_ENUMERIC;
+      }
+      if (dl < tol) break;
+    }
+  } catch (...) {
+    return CTM_EINVAL;
+  }
+  if (iters_done) *iters_done = it;
+  if (delta) *delta = dl;
+  const int st = status_from(s);
+  if (st != CTM_OK) return st;
+  return (dl < tol) ? CTM_OK : CTM_ENOTCONV;
+}
+
+int ctm_energy(ctm_solver* s, const double* h2, double* e_site, double e_bond[4]) {
+  if (!s) return CTM_EINVAL;
+  Ctx& c = s->ctx;
+  const int d = s->d;
+  std::vector<double> h(d * d * d * d, 0.0);
+  if (h2) {
+    std::memcpy(h.data(), h2, h.size() * sizeof(double));
+  } else {
+    if (d != 2) return CTM_EINVAL;
+    // S.S = (sx sx + sy sy + sz sz) / 4 in the basis (up, down)
+    const double v[16] = {0.25, 0, 0, 0, 0, -0.25, 0.5, 0, 0, 0.5, -0.25, 0, 0, 0, 0, 0.25};
+    std::memcpy(h.data(), v, sizeof(v));
+  }
+  double res[8];
+  int flag = 0;
+  try {
+    c.check(hipMemcpyAsync(s->h4, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, c.stream));
+    for (int k = 0; k < 4; ++k) bond_energy(s, k & 1, k >> 1, s->scal + 40 + 2 * k);
+    c.check(hipMemcpyAsync(res, s->scal + 40, sizeof(res), hipMemcpyDeviceToHost, c.stream));
+    c.check(hipMemcpyAsync(&flag, c.dev_flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    c.check(hipStreamSynchronize(c.stream));
+  } catch (...) {
+    return CTM_EINVAL;
+  }
+  const int st = status_from(s);
+  if (st != CTM_OK) return st;
+  double sum = 0.0;
+  bool bad = flag != 0;
+  for (int k = 0; k < 4; ++k) {
+    const double e = res[2 * k] / res[2 * k + 1];
+    if (!std::isfinite(e)) bad = true;
+    if (e_bond) e_bond[k] = e;
+    sum += e;
+  }
+  if (e_site) *e_site = 0.5 * sum;
+  return bad ? CTM_ENUMERIC : CTM_OK;
+}
+
+int ctm_get_env(ctm_solver* s, int e, double* host_out, size_t n, int* p, int* q) {
+  if (!s || e < 0 || e > 15) return CTM_EINVAL;
+  if (p) *p = s->pd[e];
+  if (q) *q = s->qd[e];
+  const size_t cnt = (e < 8) ? (size_t)s->pd[e] * s->qd[e]
+                             : (size_t)s->pd[e] * s->D * s->D * s->qd[e];
+  if (host_out) {
+    if (n < cnt) return CTM_EINVAL;
+    s->ctx.check(hipMemcpyAsync(host_out, s->env[e], cnt * sizeof(double), hipMemcpyDeviceToHost,
+                                s->ctx.stream));
+    s->ctx.check(hipStreamSynchronize(s->ctx.stream));
+  }
+  return status_from(s);
+}
+
+int ctm_set_env(ctm_solver* s, int e, const double* host_in, int p, int q) {
+  if (!s || e < 0 || e > 15 || !host_in || p < 1 || q < 1 || p > s->cap || q > s->cap)
+    return CTM_EINVAL;
+  const size_t cnt = (e < 8) ? (size_t)p * q : (size_t)p * s->D * s->D * q;
+  s->ctx.check(hipMemcpyAsync(s->env[e], host_in, cnt * sizeof(double), hipMemcpyHostToDevice,
+                              s->ctx.stream));
+  s->ctx.check(hipStreamSynchronize(s->ctx.stream));
+  s->pd[e] = p;
+  s->qd[e] = q;
+  s->spec_valid = false;
+  return status_from(s);
+}
+
+int ctm_moves_done(const ctm_solver* s) { return s ? s->moves : -1; }
+
+int ctm_set_precision(ctm_solver* s, int precision) {
+  if (!s || precision < CTM_FP64 || precision > CTM_BF16) return CTM_EINVAL;
+  if (precision == s->precision) return CTM_OK;
+  // the chain layouts of the sites are kept in the compute type; the
+  // buffers were sized for FP64, the widest type
+  s->precision = precision;
+  rebuild_chain_sites(s);
+  return status_from(s);
+}
+
+int ctm_profile(ctm_solver* s, int enable) {
+  if (!s) return CTM_EINVAL;
+  s->ctx.check(hipStreamSynchronize(s->ctx.stream));
+  s->prof.clear();
+  s->ctx.prof = enable ? &s->prof : nullptr;
+  return status_from(s);
+}
+
+int ctm_profile_read(ctm_solver* s, int cls, long long* launches, double* ms, double* flops,
+                     double* bytes) {
+  if (!s || cls < 0 || cls >= K_NCLASS) return CTM_EINVAL;
+  s->ctx.check(hipStreamSynchronize(s->ctx.stream));
+  s->prof.collect();
+  if (launches) *launches = s->prof.n[cls];
+  if (ms) *ms = s->prof.ms[cls];
+  if (flops) *flops = s->prof.flops[cls];
+  if (bytes) *bytes = s->prof.bytes[cls];
+  return status_from(s);
+}
+
+void ctm_destroy(ctm_solver* s) {
+  if (s) s->prof.clear();
+  delete s;
+}
+
+const char* ctm_status_string(int status) {
+  switch (status) {
+    case CTM_OK: return "ok";
+    case CTM_EINVAL: return "invalid argument";
+    case CTM_ENOMEM: return "workspace too small";
+    case CTM_EHIP: return "HIP runtime error";
+    case CTM_ENUMERIC: return "numerical failure (zero, NaN or Inf norm)";
+    case CTM_ENOTCONV: return "not converged within max_iters";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

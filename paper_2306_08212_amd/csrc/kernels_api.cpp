@@ -1,0 +1,62 @@
+// Kernel-level C-ABI: thin argument checks around the launch wrappers.
+#include "../../include/ctm.h"
+#include "../../include/ctm_kernels.h"
+#include "ctm_internal.h"
+
+using namespace ctm;
+
+extern "C" {
+
+int ctm_kernel_gemm(int dtype, int m, int n, int k, double alpha, const void* A, int64_t lda,
+                    int ta, const void* B, int64_t ldb, int tb, double beta, void* C,
+                    int64_t ldc, void* stream) {
+  if (dtype < 0 || dtype > 2 || m < 0 || n < 0 || k < 0 || !C) return CTM_EINVAL;
+  if (k > 0 && (!A || !B)) return CTM_EINVAL;
+  Ctx c;
+  c.stream = (hipStream_t)stream;
+  gemm(c, dtype, m, n, k, alpha, A, lda, ta, B, ldb, tb, beta, C, ldc);
+  return c.hip_err == hipSuccess ? CTM_OK : CTM_EHIP;
+}
+
+size_t ctm_kernel_tsvd_workspace(int m, int n, int k) {
+  if (m < 1 || n < 1 || k < 1) return 0;
+  Ctx c;
+  c.dry = true;
+  c.arena.dry = true;
+  tsvd(c, nullptr, m, n, k, 0.0, nullptr, nullptr);
+  return c.arena.peak + 256;
+}
+
+int ctm_kernel_tsvd(const double* M, int m, int n, int k, double tau, double* U, double* S,
+                    void* workspace, size_t workspace_bytes, void* stream) {
+  if (!M || !U || !S || m < 1 || n < 1 || k < 1 || !(tau >= 0.0)) return CTM_EINVAL;
+  if (!workspace || workspace_bytes < ctm_kernel_tsvd_workspace(m, n, k)) return CTM_ENOMEM;
+  Ctx c;
+  c.stream = (hipStream_t)stream;
+  c.arena.base = (char*)workspace;
+  c.arena.cap = workspace_bytes;
+  tsvd(c, M, m, n, k, tau, U, S);
+  if (c.arena.overflow) return CTM_ENOMEM;
+  return c.hip_err == hipSuccess ? CTM_OK : CTM_EHIP;
+}
+
+int ctm_kernel_permute(int dt_in, const void* in, int nd, const int64_t* dims, const int* perm,
+                       int dt_out, void* out, double scale, void* stream) {
+  if (!in || !out || !dims || !perm || nd < 1 || nd > kMaxDims) return CTM_EINVAL;
+  if (dt_in < 0 || dt_in > 2 || dt_out < 0 || dt_out > 2) return CTM_EINVAL;
+  bool seen[kMaxDims] = {false};
+  std::vector<int64_t> vd(dims, dims + nd), od;
+  for (int i = 0; i < nd; ++i) {
+    if (perm[i] < 0 || perm[i] >= nd || seen[perm[i]] || dims[i] < 0) return CTM_EINVAL;
+    seen[perm[i]] = true;
+    od.push_back(dims[perm[i]]);
+  }
+  Ctx c;
+  c.stream = (hipStream_t)stream;
+  Tensor ti = make_view(const_cast<void*>(in), dt_in, vd);
+  Tensor to = make_view(out, dt_out, od);
+  permute(c, ti, perm, to, scale);
+  return c.hip_err == hipSuccess ? CTM_OK : CTM_EHIP;
+}
+
+}  // extern "C"

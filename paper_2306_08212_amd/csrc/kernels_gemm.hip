@@ -1,0 +1,282 @@
+// Dense GEMM kernels on the gfx950 matrix cores.
+//
+// Every contraction of the corner-transfer move (the enlarged-corner products,
+// the ket-then-bra absorption chain, the projector applications and the
+// energy networks) is lowered to C = alpha * op(A) op(B) + beta * C on
+// row-major operands.  Three element types:
+//   F64  : v_mfma_f64_16x16x4f64, 64 x 64 tile per workgroup
+//   F32  : v_mfma_f32_32x32x2f32, 128 x 128 tile
+//   BF16 : v_mfma_f32_32x32x16_bf16 (bf16 in, fp32 accumulate/out), 128 x 128
+// Ragged edges are zero-filled on the way into LDS; nothing is read or
+// written outside [0,m) x [0,n).
+#include "ctm_internal.h"
+
+namespace ctm {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------- FP64
+
+constexpr int F64_BM = 64, F64_BN = 64, F64_BK = 16;
+
+__global__ __launch_bounds__(256) void gemm_f64_kernel(
+    int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda, int ta,
+    const double* __restrict__ B, int64_t ldb, int tb, double beta, double* __restrict__ C,
+    int64_t ldc, int64_t sA, int64_t sB, int64_t sC, int tiles_n) {
+  __shared__ double As[F64_BK][F64_BM + 2];
+  __shared__ double Bs[F64_BK][F64_BN + 2];
+  const int bz = blockIdx.y;
+  A += sA * bz;
+  B += sB * bz;
+  C += sC * bz;
+  const int tile = blockIdx.x;
+  const int m0 = (tile / tiles_n) * F64_BM, n0 = (tile % tiles_n) * F64_BN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  d4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  for (int k0 = 0; k0 < K; k0 += F64_BK) {
+    for (int e = tid; e < F64_BM * F64_BK; e += 256) {
+      int mm, kk;
+      if (!ta) { mm = e / F64_BK; kk = e % F64_BK; } else { kk = e / F64_BM; mm = e % F64_BM; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      double v = 0.0;
+      if (gm < M && gk < K) v = ta ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+      As[kk][mm] = v;
+    }
+    for (int e = tid; e < F64_BN * F64_BK; e += 256) {
+      int nn, kk;
+      if (!tb) { kk = e / F64_BN; nn = e % F64_BN; } else { nn = e / F64_BK; kk = e % F64_BK; }
+      const int gn = n0 + nn, gk = k0 + kk;
+      double v = 0.0;
+      if (gn < N && gk < K) v = tb ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+      Bs[kk][nn] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < F64_BK; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const double a0 = As[kr][wm + (lane & 15)];
+      const double a1 = As[kr][wm + 16 + (lane & 15)];
+      const double b0 = Bs[kr][wn + (lane & 15)];
+      const double b1 = Bs[kr][wn + 16 + (lane & 15)];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of 16x16x4 f64 (checked on gfx950): lane l, element r ->
+  // row l/16 + 4*r, col l%16
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
+        const int gn = n0 + wn + j * 16 + (lane & 15);
+        if (gm < M && gn < N) {
+          double* cp = C + (int64_t)gm * ldc + gn;
+          const double v = alpha * acc[i][j][r];
+          *cp = (beta == 0.0) ? v : v + beta * (*cp);
+        }
+      }
+}
+
+// ---------------------------------------------------------------- FP32
+
+constexpr int F32_BM = 128, F32_BN = 128, F32_BK = 16;
+
+__global__ __launch_bounds__(256) void gemm_f32_kernel(
+    int M, int N, int K, float alpha, const float* __restrict__ A, int64_t lda, int ta,
+    const float* __restrict__ B, int64_t ldb, int tb, float beta, float* __restrict__ C,
+    int64_t ldc, int64_t sA, int64_t sB, int64_t sC, int tiles_n) {
+  __shared__ float As[F32_BK][F32_BM + 4];
+  __shared__ float Bs[F32_BK][F32_BN + 4];
+  const int bz = blockIdx.y;
+  A += sA * bz;
+  B += sB * bz;
+  C += sC * bz;
+  const int tile = blockIdx.x;
+  const int m0 = (tile / tiles_n) * F32_BM, n0 = (tile % tiles_n) * F32_BN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f16v acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+
+  float ra[8], rb[8];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + q * 256;
+      int mm, kk;
+      if (!ta) { mm = e / F32_BK; kk = e % F32_BK; } else { kk = e / F32_BM; mm = e % F32_BM; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      float v = 0.0f;
+      if (gm < M && gk < K) v = ta ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+      ra[q] = v;
+      int nn;
+      if (!tb) { kk = e / F32_BN; nn = e % F32_BN; } else { nn = e / F32_BK; kk = e % F32_BK; }
+      const int gn = n0 + nn;
+      const int gk2 = k0 + kk;
+      float w = 0.0f;
+      if (gn < N && gk2 < K) w = tb ? B[(int64_t)gn * ldb + gk2] : B[(int64_t)gk2 * ldb + gn];
+      rb[q] = w;
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int e = tid + q * 256;
+      int mm, kk;
+      if (!ta) { mm = e / F32_BK; kk = e % F32_BK; } else { kk = e / F32_BM; mm = e % F32_BM; }
+      As[kk][mm] = ra[q];
+      int nn;
+      if (!tb) { kk = e / F32_BN; nn = e % F32_BN; } else { nn = e / F32_BK; kk = e % F32_BK; }
+      Bs[kk][nn] = rb[q];
+    }
+  };
+  load_tiles(0);
+  for (int k0 = 0; k0 < K; k0 += F32_BK) {
+    store_tiles();
+    __syncthreads();
+    if (k0 + F32_BK < K) load_tiles(k0 + F32_BK);
+#pragma unroll
+    for (int kk = 0; kk < F32_BK; kk += 2) {
+      const int kr = kk + (lane >> 5);
+      const float a0 = As[kr][wm + (lane & 31)];
+      const float a1 = As[kr][wm + 32 + (lane & 31)];
+      const float b0 = Bs[kr][wn + (lane & 31)];
+      const float b1 = Bs[kr][wn + 32 + (lane & 31)];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // D layout of 32x32 f32 (checked on gfx950): lane l, element j ->
+  // row 8*(j/4) + 4*(l/32) + j%4, col l%32
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 16; ++r) {
+        const int gm = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int gn = n0 + wn + j * 32 + (lane & 31);
+        if (gm < M && gn < N) {
+          float* cp = C + (int64_t)gm * ldc + gn;
+          const float v = alpha * acc[i][j][r];
+          *cp = (beta == 0.0f) ? v : v + beta * (*cp);
+        }
+      }
+}
+
+// ---------------------------------------------------------------- BF16
+
+constexpr int B16_BM = 128, B16_BN = 128, B16_BK = 32;
+
+// LDS holds A as [m][k] and B as [n][k] so each lane's 8 consecutive k
+// values are one 16-byte read.
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(
+    int M, int N, int K, float alpha, const __bf16* __restrict__ A, int64_t lda, int ta,
+    const __bf16* __restrict__ B, int64_t ldb, int tb, float beta, float* __restrict__ C,
+    int64_t ldc, int64_t sA, int64_t sB, int64_t sC, int tiles_n) {
+  __shared__ __attribute__((aligned(16))) __bf16 As[B16_BM][B16_BK + 8];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[B16_BN][B16_BK + 8];
+  const int bz = blockIdx.y;
+  A += sA * bz;
+  B += sB * bz;
+  C += sC * bz;
+  const int tile = blockIdx.x;
+  const int m0 = (tile / tiles_n) * B16_BM, n0 = (tile % tiles_n) * B16_BN;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  f16v acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
+  const __bf16 zero = (__bf16)0.0f;
+  for (int k0 = 0; k0 < K; k0 += B16_BK) {
+    for (int e = tid; e < B16_BM * B16_BK; e += 256) {
+      int mm, kk;
+      if (!ta) { mm = e / B16_BK; kk = e % B16_BK; } else { kk = e / B16_BM; mm = e % B16_BM; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      __bf16 v = zero;
+      if (gm < M && gk < K) v = ta ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+      As[mm][kk] = v;
+      int nn;
+      if (!tb) { kk = e / B16_BN; nn = e % B16_BN; } else { nn = e / B16_BK; kk = e % B16_BK; }
+      const int gn = n0 + nn, gk2 = k0 + kk;
+      __bf16 w = zero;
+      if (gn < N && gk2 < K) w = tb ? B[(int64_t)gn * ldb + gk2] : B[(int64_t)gk2 * ldb + gn];
+      Bs[nn][kk] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < B16_BK; kk += 16) {
+      const int kc = kk + (lane >> 5) * 8;
+      const bf8 a0 = *(const bf8*)&As[wm + (lane & 31)][kc];
+      const bf8 a1 = *(const bf8*)&As[wm + 32 + (lane & 31)][kc];
+      const bf8 b0 = *(const bf8*)&Bs[wn + (lane & 31)][kc];
+      const bf8 b1 = *(const bf8*)&Bs[wn + 32 + (lane & 31)][kc];
+      acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int r = 0; r < 16; ++r) {
+        const int gm = m0 + wm + i * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int gn = n0 + wn + j * 32 + (lane & 31);
+        if (gm < M && gn < N) {
+          float* cp = C + (int64_t)gm * ldc + gn;
+          const float v = alpha * acc[i][j][r];
+          *cp = (beta == 0.0f) ? v : v + beta * (*cp);
+        }
+      }
+}
+
+}  // namespace
+
+void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A, int64_t lda,
+          int ta, const void* B, int64_t ldb, int tb, double beta, void* C, int64_t ldc,
+          int batch, int64_t sA, int64_t sB, int64_t sC) {
+  if (c.dry || m <= 0 || n <= 0 || batch <= 0) return;
+  if (k < 0) k = 0;
+  // k == 0 needs no special case: the K loop is empty and C = beta * C.
+  const double es = dtype == F64 ? 8.0 : (dtype == F32 ? 4.0 : 2.0);
+  const double eo = dtype == F64 ? 8.0 : 4.0;
+  ProfScope ps(c, dtype == F64 ? K_GEMM_F64 : (dtype == F32 ? K_GEMM_F32 : K_GEMM_BF16),
+               2.0 * m * n * (double)k * batch,
+               ((double)m * k + (double)k * n) * es * batch + (double)m * n * eo * batch);
+  if (dtype == F64) {
+    const int tm = (m + F64_BM - 1) / F64_BM, tn = (n + F64_BN - 1) / F64_BN;
+    dim3 grid(tm * tn, batch);
+    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, c.stream, m, n, k, alpha,
+                       (const double*)A, lda, ta, (const double*)B, ldb, tb, beta, (double*)C,
+                       ldc, sA, sB, sC, tn);
+  } else if (dtype == F32) {
+    const int tm = (m + F32_BM - 1) / F32_BM, tn = (n + F32_BN - 1) / F32_BN;
+    dim3 grid(tm * tn, batch);
+    hipLaunchKernelGGL(gemm_f32_kernel, grid, dim3(256), 0, c.stream, m, n, k, (float)alpha,
+                       (const float*)A, lda, ta, (const float*)B, ldb, tb, (float)beta,
+                       (float*)C, ldc, sA, sB, sC, tn);
+  } else {
+    const int tm = (m + B16_BM - 1) / B16_BM, tn = (n + B16_BN - 1) / B16_BN;
+    dim3 grid(tm * tn, batch);
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, c.stream, m, n, k, (float)alpha,
+                       (const __bf16*)A, lda, ta, (const __bf16*)B, ldb, tb, (float)beta,
+                       (float*)C, ldc, sA, sB, sC, tn);
+  }
+  c.check_launch();
+}
+
+}  // namespace ctm

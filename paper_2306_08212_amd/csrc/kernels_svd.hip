@@ -1,0 +1,506 @@
+// FP64 truncated SVD for the chi-truncation of the corner-transfer move.
+//
+// The isometries of the move are the top-k left singular vectors of a
+// reshaped sub-network (standard isometry, the split isometries v^1, v^2 and
+// the helper isometries v_l, v_r).  They are computed here with a one-sided
+// (Hestenes) block Jacobi method:
+//
+//   X (r x c, column-major, r >= c) is orthogonalised by plane rotations
+//   applied from the right, X <- X J, until every pair of columns is
+//   orthogonal to tol relative to their norms.  Then X = U Sigma: the
+//   singular values are the column norms and the left singular vectors the
+//   normalised columns.  If M is wide (m < n) the method runs on M^T and the
+//   accumulated rotations V are the left singular vectors of M.
+//
+// Columns are grouped in blocks of 16; one workgroup takes a pair of blocks
+// (32 columns), forms their 32 x 32 Gram matrix, diagonalises it with cyclic
+// Jacobi in LDS, and applies the resulting rotation to the 32 columns of X
+// (and of V).  Block pairs follow a round-robin tournament, so the pairs of
+// one round are disjoint and run as one launch.  A device flag ends the
+// sweeps once a full sweep applied no rotation.
+//
+// Afterwards the columns are ranked by norm (ties by index), the top kk are
+// written out, columns with sigma <= tau * sigma_0 are zeroed and every kept
+// column is sign-fixed: among the rows whose magnitude is within 1e-8
+// (relative) of the largest, the lowest is made positive.  Rotations built
+// from Gram entries leave columns of small sigma orthogonal to the large ones
+// only to about eps * sigma_0 / sigma_j.  So U is taken from the accumulated
+// rotations whenever m <= n, and for strictly tall M blocked classical
+// Gram-Schmidt applied twice, in descending-sigma order, restores
+// orthonormality.
+#include <cmath>
+
+#include "ctm_internal.h"
+
+namespace ctm {
+namespace {
+
+constexpr int JW = 16;         // columns per block
+constexpr int JP = 2 * JW;     // columns per pair
+constexpr double kSignTie = 1e-8;
+
+__device__ __forceinline__ void rr_pair(int nb, int round, int i, int* a, int* b) {
+  // circle method: block 0 fixed, the others rotate
+  auto pos = [&](int k) { return ((k - 1 + round) % (nb - 1)) + 1; };
+  *a = (i == 0) ? 0 : pos(i);
+  *b = pos(nb - 1 - i);
+}
+
+// in-LDS cyclic Jacobi on the symmetric positive semi-definite 32 x 32 Gram
+// matrix G; J accumulates the rotations.  Relative stopping test and
+// Rutishauser's update of the pivot entries (a_pp - t a_pq, a_qq + t a_pq,
+// a_pq = 0) keep small entries relatively accurate, so the small entries of
+// J (those coupling columns of very different norm) are accurate too.
+__device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double tol,
+                               int* sflag, double* cs, int* pq) {
+  const int t = threadIdx.x;
+  __shared__ double piv[JP / 2][3];
+  for (int idx = t; idx < JP * JP; idx += blockDim.x) J[idx / JP][idx % JP] = (idx / JP == idx % JP) ? 1.0 : 0.0;
+  __syncthreads();
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (t == 0) *sflag = 0;
+    __syncthreads();
+    for (int round = 0; round < JP - 1; ++round) {
+      if (t < JP / 2) {
+        int p, q;
+        rr_pair(JP, round, t, &p, &q);
+        if (p > q) { const int x = p; p = q; q = x; }
+        const double app = G[p][p], aqq = G[q][q], apq = G[p][q];
+        double c = 1.0, s = 0.0, tt = 0.0;
+        if (fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+          const double tau = (aqq - app) / (2.0 * apq);
+          tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + tt * tt);
+          s = tt * c;
+          *sflag = 1;
+        }
+        cs[2 * t] = c;
+        cs[2 * t + 1] = s;
+        pq[2 * t] = p;
+        pq[2 * t + 1] = q;
+        piv[t][0] = app - tt * apq;
+        piv[t][1] = aqq + tt * apq;
+      }
+      __syncthreads();
+      // rows: G <- J^T G (pivot 2x2 blocks are set exactly below)
+      for (int task = t; task < (JP / 2) * JP; task += blockDim.x) {
+        const int i = task / JP, k = task % JP;
+        const int p = pq[2 * i], q = pq[2 * i + 1];
+        const double c = cs[2 * i], s = cs[2 * i + 1];
+        if (s != 0.0 && k != p && k != q) {
+          const double gp = G[p][k], gq = G[q][k];
+          G[p][k] = c * gp - s * gq;
+          G[q][k] = s * gp + c * gq;
+        }
+      }
+      __syncthreads();
+      // columns: G <- G J, J <- J J
+      for (int task = t; task < (JP / 2) * JP; task += blockDim.x) {
+        const int i = task / JP, k = task % JP;
+        const int p = pq[2 * i], q = pq[2 * i + 1];
+        const double c = cs[2 * i], s = cs[2 * i + 1];
+        if (s != 0.0) {
+          if (k != p && k != q) {
+            const double gp = G[k][p], gq = G[k][q];
+            G[k][p] = c * gp - s * gq;
+            G[k][q] = s * gp + c * gq;
+          }
+          const double jp = J[k][p], jq = J[k][q];
+          J[k][p] = c * jp - s * jq;
+          J[k][q] = s * jp + c * jq;
+        }
+      }
+      __syncthreads();
+      if (t < JP / 2 && cs[2 * t + 1] != 0.0) {
+        const int p = pq[2 * t], q = pq[2 * t + 1];
+        G[p][p] = piv[t][0];
+        G[q][q] = piv[t][1];
+        G[p][q] = 0.0;
+        G[q][p] = 0.0;
+      }
+      __syncthreads();
+    }
+    if (*sflag == 0) break;
+    __syncthreads();
+  }
+}
+
+// X: r rows, ld = ldx, column-major.  V: vr rows (0 = none), ld = vr.
+__global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, int r, int64_t ldx,
+                                                        double* __restrict__ V, int vr, int nb,
+                                                        int round, double tol, double tol_in,
+                                                        int* __restrict__ flags) {
+  __shared__ double G[JP][JP + 1];
+  __shared__ double J[JP][JP + 1];
+  __shared__ double chunk[32][JP + 1];
+  __shared__ double cs[JP];
+  __shared__ int pq[JP];
+  __shared__ int any, sflag;
+  if (flags[0]) return;   // converged in an earlier sweep
+  int bi, bj;
+  rr_pair(nb, round, blockIdx.x, &bi, &bj);
+  const int t = threadIdx.x;
+  auto col = [&](int a) { return a < JW ? bi * JW + a : bj * JW + (a - JW); };
+
+  // Gram of the 32 columns
+  const int ga = t >> 3, gb = (t & 7) * 4;
+  double g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+  for (int row0 = 0; row0 < r; row0 += 32) {
+    for (int e = t; e < 32 * JP; e += 256) {
+      const int a = e >> 5, rr = e & 31;
+      const int gr = row0 + rr;
+      chunk[rr][a] = gr < r ? X[(int64_t)col(a) * ldx + gr] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < 32; ++rr) {
+      const double x = chunk[rr][ga];
+      g0 += x * chunk[rr][gb];
+      g1 += x * chunk[rr][gb + 1];
+      g2 += x * chunk[rr][gb + 2];
+      g3 += x * chunk[rr][gb + 3];
+    }
+    __syncthreads();
+  }
+  G[ga][gb] = g0;
+  G[ga][gb + 1] = g1;
+  G[ga][gb + 2] = g2;
+  G[ga][gb + 3] = g3;
+  if (t == 0) any = 0;
+  __syncthreads();
+  for (int q = 0; q < 4; ++q) {
+    const int b = gb + q;
+    if (b != ga) {
+      const double gab = G[ga][b], gaa = G[ga][ga], gbb = G[b][b];
+      if (fabs(gab) > tol * sqrt(fabs(gaa * gbb))) any = 1;
+    }
+  }
+  __syncthreads();
+  if (!any) return;
+  lds_sym_jacobi(G, J, tol_in, &sflag, cs, pq);
+  if (t == 0) atomicAdd(&flags[1], 1);
+
+  // X[:, cols] <- X[:, cols] J   (thread: column b = t/8, 4 consecutive rows)
+  const int ob = t >> 3, orr = (t & 7) * 4;
+  for (int row0 = 0; row0 < r; row0 += 32) {
+    for (int e = t; e < 32 * JP; e += 256) {
+      const int a = e >> 5, rr = e & 31;
+      const int gr = row0 + rr;
+      chunk[rr][a] = gr < r ? X[(int64_t)col(a) * ldx + gr] : 0.0;
+    }
+    __syncthreads();
+    double o[4] = {0, 0, 0, 0};
+    for (int a = 0; a < JP; ++a) {
+      const double j = J[a][ob];
+      for (int q = 0; q < 4; ++q) o[q] += chunk[orr + q][a] * j;
+    }
+    for (int q = 0; q < 4; ++q) {
+      const int gr = row0 + orr + q;
+      if (gr < r) X[(int64_t)col(ob) * ldx + gr] = o[q];
+    }
+    __syncthreads();
+  }
+  if (V != nullptr) {
+    for (int row0 = 0; row0 < vr; row0 += 32) {
+      for (int e = t; e < 32 * JP; e += 256) {
+        const int a = e >> 5, rr = e & 31;
+        const int gr = row0 + rr;
+        chunk[rr][a] = gr < vr ? V[(int64_t)col(a) * vr + gr] : 0.0;
+      }
+      __syncthreads();
+      double o[4] = {0, 0, 0, 0};
+      for (int a = 0; a < JP; ++a) {
+        const double j = J[a][ob];
+        for (int q = 0; q < 4; ++q) o[q] += chunk[orr + q][a] * j;
+      }
+      for (int q = 0; q < 4; ++q) {
+        const int gr = row0 + orr + q;
+        if (gr < vr) V[(int64_t)col(ob) * vr + gr] = o[q];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void jac_sweep_end(int* flags) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (flags[0] == 0 && flags[1] == 0) flags[0] = 1;
+    flags[1] = 0;
+  }
+}
+
+__global__ void jac_flags_init(int* flags) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    flags[0] = 0;
+    flags[1] = 0;
+  }
+}
+
+// X (col-major, r x cp) from row-major M (m x n).  transpose: X = M (m >= n),
+// else X = M^T.  Padded columns are zero.  V = identity on c columns.
+__global__ __launch_bounds__(256) void jac_prep_kernel(const double* __restrict__ M, int m, int n,
+                                                       int tall, double* __restrict__ X, int r,
+                                                       int cp, double* __restrict__ V, int vr) {
+  const int64_t total = (int64_t)r * cp;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
+    const int j = (int)(e / r), i = (int)(e % r);
+    double v = 0.0;
+    if (tall) {
+      if (j < n) v = M[(int64_t)i * n + j];   // X[:, j] = column j of M
+    } else {
+      if (j < m) v = M[(int64_t)j * n + i];   // X[:, j] = row j of M
+    }
+    X[e] = v;
+  }
+  if (V != nullptr) {
+    const int64_t tv = (int64_t)vr * cp;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tv; e += (int64_t)gridDim.x * 256) {
+      const int j = (int)(e / vr), i = (int)(e % vr);
+      V[e] = (i == j) ? 1.0 : 0.0;
+    }
+  }
+}
+
+// column norms -> sig[cp]
+__global__ __launch_bounds__(256) void jac_colnorm_kernel(const double* __restrict__ X, int r,
+                                                          int cp, double* __restrict__ sig) {
+  __shared__ double sh[256];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < r; i += 256) {
+    const double v = X[(int64_t)j * r + i];
+    s += v * v;
+  }
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sig[j] = sqrt(sh[0]);
+}
+
+// order[rank] = column, for ranks < kk (descending norm, ties by index)
+__global__ __launch_bounds__(256) void jac_rank_kernel(const double* __restrict__ sig, int c, int kk,
+                                                       int* __restrict__ order) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= c) return;
+  const double v = sig[j];
+  int rank = 0;
+  for (int i = 0; i < c; ++i) {
+    const double w = sig[i];
+    rank += (w > v) || (w == v && i < j);
+  }
+  if (rank < kk) order[rank] = j;
+}
+
+// U[:, t] (row-major m x kk) and S[t]; one workgroup per output column.
+__global__ __launch_bounds__(256) void jac_output_kernel(const double* __restrict__ X, int r,
+                                                         const double* __restrict__ V, int vr,
+                                                         const double* __restrict__ sig,
+                                                         const int* __restrict__ order, int m,
+                                                         int kk, double tau,
+                                                         double* __restrict__ U,
+                                                         double* __restrict__ S) {
+  __shared__ double shm[256];
+  __shared__ int shi[256];
+  const int t = blockIdx.x;
+  const int j = order[t];
+  const double s0 = sig[order[0]];
+  const double sj = sig[j];
+  const bool keep = (s0 > 0.0) && (sj > tau * s0) && isfinite(sj);
+  // source column: normalised X column (tall) or V column (wide)
+  auto src = [&](int i) -> double {
+    if (V != nullptr) return V[(int64_t)j * vr + i];
+    return X[(int64_t)j * r + i] / sj;
+  };
+  if (!keep) {
+    for (int i = threadIdx.x; i < m; i += 256) U[(int64_t)i * kk + t] = 0.0;
+    if (threadIdx.x == 0) S[t] = 0.0;
+    return;
+  }
+  // largest magnitude
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) mx = fmax(mx, fabs(src(i)));
+  shm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double thr = (1.0 - kSignTie) * shm[0];
+  __syncthreads();
+  // lowest row within the tie band
+  int lo = 0x7fffffff;
+  for (int i = threadIdx.x; i < m; i += 256)
+    if (fabs(src(i)) >= thr && i < lo) lo = i;
+  shi[threadIdx.x] = lo;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) shi[threadIdx.x] = min(shi[threadIdx.x], shi[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double sgn = src(shi[0]) < 0.0 ? -1.0 : 1.0;
+  for (int i = threadIdx.x; i < m; i += 256) U[(int64_t)i * kk + t] = sgn * src(i);
+  if (threadIdx.x == 0) S[t] = sj;
+}
+
+// Orthonormalise columns [c0, c0 + nb) of the row-major m x kk matrix U in
+// place, in order, by classical Gram-Schmidt applied twice within the block
+// (earlier blocks are projected out beforehand with GEMMs).  Columns whose
+// singular value was cut (S == 0) stay zero.
+__global__ __launch_bounds__(256) void cgs2_block_kernel(double* __restrict__ U, int m, int kk,
+                                                         int c0, int nb,
+                                                         const double* __restrict__ S) {
+  __shared__ double red[32][257];
+  __shared__ double coef[32];
+  const int t = threadIdx.x;
+  for (int j = 0; j < nb; ++j) {
+    const int cj = c0 + j;
+    if (!(S[cj] > 0.0)) {
+      for (int i = t; i < m; i += 256) U[(int64_t)i * kk + cj] = 0.0;
+      __syncthreads();
+      continue;
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      if (j > 0) {
+        double part[32];
+        for (int a = 0; a < j; ++a) part[a] = 0.0;
+        for (int i = t; i < m; i += 256) {
+          const double x = U[(int64_t)i * kk + cj];
+          for (int a = 0; a < j; ++a) part[a] += U[(int64_t)i * kk + c0 + a] * x;
+        }
+        for (int a = 0; a < j; ++a) red[a][t] = part[a];
+        __syncthreads();
+        if (t < j) {
+          double sacc = 0.0;
+          for (int q = 0; q < 256; ++q) sacc += red[t][q];
+          coef[t] = sacc;
+        }
+        __syncthreads();
+        for (int i = t; i < m; i += 256) {
+          double x = U[(int64_t)i * kk + cj];
+          for (int a = 0; a < j; ++a) x -= coef[a] * U[(int64_t)i * kk + c0 + a];
+          U[(int64_t)i * kk + cj] = x;
+        }
+        __syncthreads();
+      }
+    }
+    double sq = 0.0;
+    for (int i = t; i < m; i += 256) {
+      const double x = U[(int64_t)i * kk + cj];
+      sq += x * x;
+    }
+    red[0][t] = sq;
+    __syncthreads();
+    if (t == 0) {
+      double sacc = 0.0;
+      for (int q = 0; q < 256; ++q) sacc += red[0][q];
+      coef[0] = sacc > 0.0 ? 1.0 / sqrt(sacc) : 0.0;
+    }
+    __syncthreads();
+    const double inv = coef[0];
+    for (int i = t; i < m; i += 256) U[(int64_t)i * kk + cj] *= inv;
+    __syncthreads();
+  }
+}
+
+__global__ void spec_finish_kernel(const double* __restrict__ S, int kk, int chi,
+                                   double* __restrict__ out) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= chi) return;
+  const double s0 = S[0];
+  out[i] = (i < kk && s0 > 0.0) ? S[i] / s0 : 0.0;
+}
+
+}  // namespace
+
+void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, double* S) {
+  const int kk = std::min(k, std::min(m, n));
+  if (kk <= 0) return;
+  // U comes from the accumulated rotations (orthonormal by construction)
+  // unless M is strictly tall, where it is the normalised columns of M V
+  const bool tall = m > n;
+  const int r = tall ? m : n;       // rows of X
+  const int cc = tall ? n : m;      // columns of X
+  int nb = (cc + JW - 1) / JW;
+  if (nb < 2) nb = 2;
+  if (nb & 1) ++nb;
+  const int cp = nb * JW;
+  const size_t mk = c.arena.mark();
+  double* X = (double*)c.arena.alloc((size_t)r * cp * sizeof(double));
+  double* V = tall ? nullptr : (double*)c.arena.alloc((size_t)cc * cp * sizeof(double));
+  double* sig = (double*)c.arena.alloc((size_t)cp * sizeof(double));
+  int* order = (int*)c.arena.alloc((size_t)kk * sizeof(int));
+  int* flags = (int*)c.arena.alloc(2 * sizeof(int));
+  double* Ut = (double*)c.arena.alloc((size_t)m * kk * sizeof(double));
+  double* G = (double*)c.arena.alloc((size_t)kk * kk * sizeof(double));
+  if (!c.dry) {
+    int64_t blocks = ((int64_t)r * cp + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(jac_prep_kernel, dim3((unsigned)blocks), dim3(256), 0, c.stream, M, m, n,
+                       tall ? 1 : 0, X, r, cp, V, cc);
+    hipLaunchKernelGGL(jac_flags_init, dim3(1), dim3(1), 0, c.stream, flags);
+    const double eps = 2.220446049250313e-16;
+    const double tol = std::max(std::sqrt((double)r) * eps, 4 * eps);
+    const double tol_in = 4 * eps;
+    const int max_sweeps = 16;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+      for (int rd = 0; rd < nb - 1; ++rd) {
+        // work of one round if every pair rotates: Gram + update of X (and V)
+        ProfScope ps(c, K_SVD_ROUND,
+                     (double)(nb / 2) * JP * JP * 2.0 * (2.0 * r + (tall ? 0.0 : 2.0 * cc)),
+                     (double)(nb / 2) * JP * 8.0 * (3.0 * r + (tall ? 0.0 : 2.0 * cc)));
+        hipLaunchKernelGGL(jac_round_kernel, dim3(nb / 2), dim3(256), 0, c.stream, X, r,
+                           (int64_t)r, V, tall ? 0 : cc, nb, rd, tol, tol_in, flags);
+      }
+      hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(1), 0, c.stream, flags);
+    }
+    hipLaunchKernelGGL(jac_colnorm_kernel, dim3(cp), dim3(256), 0, c.stream, X, r, cp, sig);
+    hipLaunchKernelGGL(jac_rank_kernel, dim3((cp + 255) / 256), dim3(256), 0, c.stream, sig, cp,
+                       kk, order);
+    hipLaunchKernelGGL(jac_output_kernel, dim3(kk), dim3(256), 0, c.stream, X, r, V, cc, sig,
+                       order, m, kk, tau, Ut, S);
+    c.check_launch();
+  }
+  if (!c.dry)
+    c.check(hipMemcpyAsync(U, Ut, sizeof(double) * (size_t)m * kk, hipMemcpyDeviceToDevice,
+                           c.stream));
+  if (tall) {
+    // blocked CGS2 in descending-sigma order: project out earlier blocks
+    // twice (GEMMs), then orthonormalise within the block
+    constexpr int OB = 32;
+    for (int c0 = 0; c0 < kk; c0 += OB) {
+      const int nbk = std::min(OB, kk - c0);
+      if (c0 > 0) {
+        for (int pass = 0; pass < 2; ++pass) {
+          // G[0:c0, 0:nbk] = U[:, :c0]^T U[:, c0:c0+nbk]
+          gemm(c, F64, c0, nbk, m, 1.0, U, kk, 1, U + c0, kk, 0, 0.0, G, nbk);
+          // U[:, c0:] -= U[:, :c0] G
+          gemm(c, F64, m, nbk, c0, -1.0, U, kk, 0, G, nbk, 0, 1.0, U + c0, kk);
+        }
+      }
+      if (!c.dry) {
+        hipLaunchKernelGGL(cgs2_block_kernel, dim3(1), dim3(256), 0, c.stream, U, m, kk, c0, nbk, S);
+        c.check_launch();
+      }
+    }
+  }
+  c.arena.release(mk);
+}
+
+void corner_spectrum(Ctx& c, const double* C, int p, int q, int chi, double* out) {
+  const int kk = std::min(chi, std::min(p, q));
+  const size_t mk = c.arena.mark();
+  double* U = (double*)c.arena.alloc((size_t)p * std::max(kk, 1) * sizeof(double));
+  double* S = (double*)c.arena.alloc((size_t)std::max(kk, 1) * sizeof(double));
+  tsvd(c, C, p, q, chi, 0.0, U, S);
+  if (!c.dry) {
+    hipLaunchKernelGGL(spec_finish_kernel, dim3((chi + 255) / 256), dim3(256), 0, c.stream, S, kk,
+                       chi, out);
+    c.check_launch();
+  }
+  c.arena.release(mk);
+}
+
+}  // namespace ctm

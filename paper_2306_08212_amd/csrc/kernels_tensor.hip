@@ -1,0 +1,389 @@
+// Index permutes, casts and reductions (HBM-bound kernels).
+//
+// The permute regroups tensor legs between the contractions of the move so
+// that contracted legs are contiguous for the GEMM.  When the innermost leg
+// survives it is a streaming copy; otherwise a 32 x 32 LDS tile transposes the
+// input-innermost and output-innermost legs so that both the reads and the
+// writes are coalesced.  All reductions are two-pass with a fixed block
+// count and a fixed summation order, so results are bitwise reproducible.
+#include <cmath>
+
+#include "ctm_internal.h"
+
+namespace ctm {
+namespace {
+
+struct PermArgs {
+  int nd;
+  int64_t dims[kMaxDims];   // by input dim
+  int64_t sin[kMaxDims];    // input stride of each input dim
+  int64_t sout[kMaxDims];   // output stride of each input dim
+};
+
+template <typename T> __device__ __forceinline__ double ld(const T* p, int64_t i) {
+  return (double)p[i];
+}
+template <> __device__ __forceinline__ double ld<__bf16>(const __bf16* p, int64_t i) {
+  return (double)(float)p[i];
+}
+template <typename T> __device__ __forceinline__ void st(T* p, int64_t i, double v) {
+  p[i] = (T)v;
+}
+template <> __device__ __forceinline__ void st<float>(float* p, int64_t i, double v) {
+  p[i] = (float)v;
+}
+template <> __device__ __forceinline__ void st<__bf16>(__bf16* p, int64_t i, double v) {
+  p[i] = (__bf16)(float)v;
+}
+
+// innermost input dim is also the innermost output dim: rows are copied
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void permute_rows_kernel(const Ti* __restrict__ in,
+                                                            To* __restrict__ out, PermArgs a,
+                                                            int64_t total, double scale) {
+  const int64_t inner = a.dims[a.nd - 1];
+  for (int64_t o = (int64_t)blockIdx.x * 256 + threadIdx.x; o < total;
+       o += (int64_t)gridDim.x * 256) {
+    int64_t rem = o / inner;
+    const int64_t x = o - rem * inner;
+    int64_t oi = x, oo = x;
+    for (int d = a.nd - 2; d >= 0; --d) {
+      const int64_t cd = rem % a.dims[d];
+      rem /= a.dims[d];
+      oi += cd * a.sin[d];
+      oo += cd * a.sout[d];
+    }
+    st(out, oo, ld(in, oi) * scale);
+  }
+}
+
+// general case: tile over (input innermost dim ia, output innermost dim ib)
+template <typename Ti, typename To>
+__global__ __launch_bounds__(256) void permute_tile_kernel(const Ti* __restrict__ in,
+                                                            To* __restrict__ out, PermArgs a,
+                                                            int ia, int ib, int64_t ntA,
+                                                            int64_t ntB, double scale) {
+  __shared__ double tile[32][33];
+  int64_t bid = blockIdx.x;
+  const int64_t tA = bid % ntA;
+  bid /= ntA;
+  const int64_t tB = bid % ntB;
+  int64_t rest = bid / ntB;
+  int64_t bi = 0, bo = 0;
+  for (int d = a.nd - 1; d >= 0; --d) {
+    if (d == ia || d == ib) continue;
+    const int64_t cd = rest % a.dims[d];
+    rest /= a.dims[d];
+    bi += cd * a.sin[d];
+    bo += cd * a.sout[d];
+  }
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  const int64_t NA = a.dims[ia], NB = a.dims[ib];
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t xa = tA * 32 + tx, xb = tB * 32 + j;
+    double v = 0.0;
+    if (xa < NA && xb < NB) v = ld(in, bi + xa * a.sin[ia] + xb * a.sin[ib]);
+    tile[j][tx] = v;
+  }
+  __syncthreads();
+  for (int j = ty; j < 32; j += 8) {
+    const int64_t xb = tB * 32 + tx, xa = tA * 32 + j;
+    if (xa < NA && xb < NB) st(out, bo + xa * a.sout[ia] + xb * a.sout[ib], tile[tx][j] * scale);
+  }
+}
+
+template <typename Ti, typename To>
+void launch_permute(Ctx& c, const void* in, void* out, const PermArgs& a, double scale) {
+  int64_t total = 1;
+  for (int d = 0; d < a.nd; ++d) total *= a.dims[d];
+  if (total == 0) return;
+  // which input dim is innermost in the output?
+  int ib = 0;
+  for (int d = 0; d < a.nd; ++d)
+    if (a.sout[d] == 1 && a.dims[d] > 1) ib = d;
+  const int ia = a.nd - 1;
+  if (a.nd == 1 || ib == ia || a.dims[ib] == 1) {
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((permute_rows_kernel<Ti, To>), dim3((unsigned)blocks), dim3(256), 0,
+                       c.stream, (const Ti*)in, (To*)out, a, total, scale);
+  } else {
+    const int64_t ntA = (a.dims[ia] + 31) / 32, ntB = (a.dims[ib] + 31) / 32;
+    const int64_t rest = total / (a.dims[ia] * a.dims[ib]);
+    const int64_t blocks = ntA * ntB * rest;
+    hipLaunchKernelGGL((permute_tile_kernel<Ti, To>), dim3((unsigned)blocks), dim3(256), 0,
+                       c.stream, (const Ti*)in, (To*)out, a, ia, ib, ntA, ntB, scale);
+  }
+  c.check_launch();
+}
+
+__global__ void fill_kernel_f64(double* p, int64_t n, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = v;
+}
+__global__ void fill_kernel_f32(float* p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = v;
+}
+__global__ void fill_kernel_bf16(__bf16* p, int64_t n, float v) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = (__bf16)v;
+}
+
+constexpr int kRedBlocks = 512;
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  // 256 threads: wave reduction via LDS tree (fixed order)
+  sh[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  return sh[0];
+}
+
+__global__ __launch_bounds__(256) void sumsq_partial(const double* __restrict__ x, int64_t n,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)kRedBlocks * 256) {
+    const double v = x[i];
+    s += v * v;
+  }
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(256) void sumsq_final(const double* __restrict__ part,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += 256) s += part[i];
+  const double t = block_sum(s, sh);
+  if (threadIdx.x == 0) out[0] = sqrt(t);
+}
+
+__global__ __launch_bounds__(256) void scale_inv_kernel(double* __restrict__ x, int64_t n,
+                                                        const double* __restrict__ nrm,
+                                                        int* __restrict__ flags) {
+  const double v = nrm[0];
+  const bool bad = !(v > 0.0) || !isfinite(v);
+  if (bad) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 1;
+    return;
+  }
+  const double s = 1.0 / v;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    x[i] *= s;
+}
+
+__global__ __launch_bounds__(256) void max_abs_diff_kernel(const double* a, const double* b, int n,
+                                                           double* out) {
+  __shared__ double sh[256];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, fabs(a[i] - b[i]));
+  sh[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = sh[0];
+}
+
+// rho[s1,s2,s1',s2'] (ket first); h4[s1',s2',s1,s2] = h[(s1' s2'),(s1 s2)]
+__global__ void rho_energy_kernel(const double* rho, const double* h4, int d, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double num = 0.0, den = 0.0;
+  for (int s = 0; s < d; ++s)
+    for (int t = 0; t < d; ++t) {
+      den += rho[((s * d + t) * d + s) * d + t];
+      for (int S = 0; S < d; ++S)
+        for (int T = 0; T < d; ++T)
+          num += rho[((s * d + t) * d + S) * d + T] * h4[((S * d + T) * d + s) * d + t];
+    }
+  out[0] = num;
+  out[1] = den;
+}
+
+}  // namespace
+
+Tensor make_view(void* p, int dt, std::initializer_list<int64_t> dims) {
+  Tensor t;
+  t.p = p;
+  t.dt = dt;
+  t.nd = 0;
+  for (int64_t d : dims) t.dims[t.nd++] = d;
+  return t;
+}
+
+Tensor make_view(void* p, int dt, const std::vector<int64_t>& dims) {
+  Tensor t;
+  t.p = p;
+  t.dt = dt;
+  t.nd = (int)dims.size();
+  for (int i = 0; i < t.nd; ++i) t.dims[i] = dims[i];
+  return t;
+}
+
+void* Arena::alloc(size_t bytes) {
+  const size_t al = 256;
+  size_t off = (top + al - 1) / al * al;
+  top = off + bytes;
+  if (top > peak) peak = top;
+  if (!dry && top > cap) {
+    overflow = true;
+    return nullptr;
+  }
+  return (void*)(base + off);
+}
+
+Tensor Ctx::alloc(int dt, std::initializer_list<int64_t> dims) {
+  Tensor t = make_view(nullptr, dt, dims);
+  t.p = arena.alloc(t.bytes());
+  return t;
+}
+
+Tensor Ctx::alloc(int dt, const std::vector<int64_t>& dims) {
+  Tensor t = make_view(nullptr, dt, dims);
+  t.p = arena.alloc(t.bytes());
+  return t;
+}
+
+void Profiler::collect() {
+  for (Rec& r : recs) {
+    float ms_ = 0.0f;
+    if (hipEventElapsedTime(&ms_, r.e0, r.e1) == hipSuccess) {
+      n[r.cls] += 1;
+      ms[r.cls] += ms_;
+      flops[r.cls] += r.flops;
+      bytes[r.cls] += r.bytes;
+    }
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  recs.clear();
+}
+
+void Profiler::clear() {
+  for (Rec& r : recs) {
+    (void)hipEventDestroy(r.e0);
+    (void)hipEventDestroy(r.e1);
+  }
+  recs.clear();
+  for (int i = 0; i < K_NCLASS; ++i) {
+    n[i] = 0;
+    ms[i] = flops[i] = bytes[i] = 0.0;
+  }
+}
+
+void permute(Ctx& c, const Tensor& in, const int* perm, Tensor& out, double scale) {
+  if (c.dry || in.numel() == 0) return;
+  ProfScope ps(c, K_PERMUTE, 0.0,
+               (double)in.numel() * (double)(dtype_size(in.dt) + dtype_size(out.dt)));
+  // merge input dims that stay adjacent and in order; drop size-1 dims
+  int nd = in.nd;
+  int64_t ostr[kMaxDims];
+  {
+    int64_t s = 1;
+    for (int i = nd - 1; i >= 0; --i) {
+      ostr[perm[i]] = s;
+      s *= in.dims[perm[i]];
+    }
+  }
+  PermArgs a;
+  a.nd = 0;
+  int64_t istr[kMaxDims];
+  {
+    int64_t s = 1;
+    for (int i = nd - 1; i >= 0; --i) {
+      istr[i] = s;
+      s *= in.dims[i];
+    }
+  }
+  for (int i = 0; i < nd; ++i) {
+    if (in.dims[i] == 1) continue;
+    if (a.nd > 0) {
+      const int j = a.nd - 1;
+      // previous kept dim j can absorb dim i if dim i follows it in both orders
+      if (a.sin[j] == istr[i] * in.dims[i] && a.sout[j] == ostr[i] * in.dims[i]) {
+        a.dims[j] *= in.dims[i];
+        a.sin[j] = istr[i];
+        a.sout[j] = ostr[i];
+        continue;
+      }
+    }
+    a.dims[a.nd] = in.dims[i];
+    a.sin[a.nd] = istr[i];
+    a.sout[a.nd] = ostr[i];
+    ++a.nd;
+  }
+  if (a.nd == 0) {
+    a.nd = 1;
+    a.dims[0] = 1;
+    a.sin[0] = 1;
+    a.sout[0] = 1;
+  }
+#define CTM_PERM(TI, TO) launch_permute<TI, TO>(c, in.p, out.p, a, scale)
+  if (in.dt == F64 && out.dt == F64) CTM_PERM(double, double);
+  else if (in.dt == F64 && out.dt == F32) CTM_PERM(double, float);
+  else if (in.dt == F64 && out.dt == BF16) CTM_PERM(double, __bf16);
+  else if (in.dt == F32 && out.dt == F64) CTM_PERM(float, double);
+  else if (in.dt == F32 && out.dt == F32) CTM_PERM(float, float);
+  else if (in.dt == F32 && out.dt == BF16) CTM_PERM(float, __bf16);
+  else if (in.dt == BF16 && out.dt == F64) CTM_PERM(__bf16, double);
+  else if (in.dt == BF16 && out.dt == F32) CTM_PERM(__bf16, float);
+  else CTM_PERM(__bf16, __bf16);
+#undef CTM_PERM
+}
+
+void fill(Ctx& c, void* p, int dt, int64_t n, double v) {
+  if (c.dry || n <= 0) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (dt == F64)
+    hipLaunchKernelGGL(fill_kernel_f64, dim3((unsigned)blocks), dim3(256), 0, c.stream,
+                       (double*)p, n, v);
+  else if (dt == F32)
+    hipLaunchKernelGGL(fill_kernel_f32, dim3((unsigned)blocks), dim3(256), 0, c.stream,
+                       (float*)p, n, (float)v);
+  else
+    hipLaunchKernelGGL(fill_kernel_bf16, dim3((unsigned)blocks), dim3(256), 0, c.stream,
+                       (__bf16*)p, n, (float)v);
+  c.check_launch();
+}
+
+void norm2(Ctx& c, const double* x, int64_t n, double* nrm) {
+  double* part = (double*)c.arena.alloc(kRedBlocks * sizeof(double));
+  if (c.dry) return;
+  ProfScope ps(c, K_REDUCE, 2.0 * n, 8.0 * n);
+  hipLaunchKernelGGL(sumsq_partial, dim3(kRedBlocks), dim3(256), 0, c.stream, x, n, part);
+  hipLaunchKernelGGL(sumsq_final, dim3(1), dim3(256), 0, c.stream, part, nrm);
+  c.check_launch();
+}
+
+void scale_by_inv(Ctx& c, double* x, int64_t n, const double* nrm) {
+  if (c.dry) return;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  ProfScope ps(c, K_REDUCE, (double)n, 16.0 * n);
+  hipLaunchKernelGGL(scale_inv_kernel, dim3((unsigned)blocks), dim3(256), 0, c.stream, x, n, nrm,
+                     c.dev_flags);
+  c.check_launch();
+}
+
+void max_abs_diff(Ctx& c, const double* a, const double* b, int n, double* out) {
+  if (c.dry) return;
+  hipLaunchKernelGGL(max_abs_diff_kernel, dim3(1), dim3(256), 0, c.stream, a, b, n, out);
+  c.check_launch();
+}
+
+void rho_energy(Ctx& c, const double* rho, const double* h4, int d, double* out) {
+  if (c.dry) return;
+  hipLaunchKernelGGL(rho_energy_kernel, dim3(1), dim3(64), 0, c.stream, rho, h4, d, out);
+  c.check_launch();
+}
+
+}  // namespace ctm

@@ -1,0 +1,119 @@
+"""Kernel-level parity of the HIP library against plain references.
+
+GEMM and permute are checked against float64 products on the CPU; the
+truncated SVD against the oracle's LAPACK-based truncate (same cutoff and
+sign rule)."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+from gpu_util import dev, gemm, log, permute, torch, tsvd
+from synth import random_orthogonal
+
+pytestmark = pytest.mark.gpu
+
+
+GEMM_SHAPES = [(1, 1, 1), (16, 16, 4), (77, 130, 45), (128, 128, 16), (200, 3, 513),
+               (513, 257, 64), (64, 2048, 256), (1000, 64, 8)]
+
+
+@pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_fp64(m, n, k, ta, tb):
+    log("gemm f64", m, n, k, ta, tb)
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    A = rng.standard_normal((k, m) if ta else (m, k))
+    B = rng.standard_normal((n, k) if tb else (k, n))
+    ref = (A.T if ta else A) @ (B.T if tb else B)
+    C = gemm(0, dev(A), dev(B), ta, tb).cpu().numpy()
+    np.testing.assert_allclose(C, ref, rtol=0, atol=1e-12 * np.sqrt(k) * max(1, np.abs(ref).max()))
+
+
+@pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1)])
+def test_gemm_fp32_and_bf16(m, n, k, ta, tb):
+    log("gemm f32/bf16", m, n, k, ta, tb)
+    t = torch()
+    rng = np.random.default_rng(m + n + k)
+    A = rng.standard_normal((k, m) if ta else (m, k)).astype(np.float32)
+    B = rng.standard_normal((n, k) if tb else (k, n)).astype(np.float32)
+    ref = (A.T.astype(np.float64) if ta else A.astype(np.float64)) @ \
+        (B.T.astype(np.float64) if tb else B.astype(np.float64))
+    C = gemm(1, dev(A), dev(B), ta, tb).cpu().numpy()
+    scale = np.sqrt(k) * max(1.0, np.abs(ref).max())
+    np.testing.assert_allclose(C, ref, rtol=0, atol=2e-6 * scale)
+    Ab = dev(A, t.bfloat16)
+    Bb = dev(B, t.bfloat16)
+    refb = (Ab.double().cpu().numpy().T if ta else Ab.double().cpu().numpy()) @ \
+        (Bb.double().cpu().numpy().T if tb else Bb.double().cpu().numpy())
+    Cb = gemm(2, Ab, Bb, ta, tb).cpu().numpy()
+    np.testing.assert_allclose(Cb, refb, rtol=0, atol=2e-6 * scale)
+
+
+def test_gemm_beta_accumulates():
+    rng = np.random.default_rng(1)
+    A, B, C0 = rng.standard_normal((33, 17)), rng.standard_normal((17, 65)), rng.standard_normal((33, 65))
+    C = dev(C0)
+    gemm(0, dev(A), dev(B), alpha=2.0, beta=-0.5, C=C)
+    np.testing.assert_allclose(C.cpu().numpy(), 2.0 * A @ B - 0.5 * C0, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape,perm", [((3, 5, 7), (2, 0, 1)), ((64, 64), (1, 0)),
+                                         ((2, 8, 8, 8, 8), (0, 2, 1, 4, 3)),
+                                         ((33, 2, 40, 9), (3, 1, 0, 2)),
+                                         ((4, 5, 6, 7, 8, 3), (5, 4, 3, 2, 1, 0)),
+                                         ((100, 1, 37), (2, 1, 0)), ((1000,), (0,))])
+def test_permute_and_cast(shape, perm):
+    log("permute", shape, perm)
+    t = torch()
+    rng = np.random.default_rng(len(shape))
+    x = rng.standard_normal(shape)
+    ref = np.transpose(x, perm)
+    y = permute(dev(x), perm, 0, 0).cpu().numpy()
+    assert np.array_equal(y, ref)
+    y32 = permute(dev(x), perm, 0, 1, scale=0.5).cpu().numpy()
+    np.testing.assert_allclose(y32, 0.5 * ref.astype(np.float32), rtol=1e-7)
+    yb = permute(dev(x.astype(np.float32)), perm, 1, 2).float().cpu().numpy()
+    refb = t.from_numpy(ref.astype(np.float32)).to(t.bfloat16).float().numpy()
+    assert np.array_equal(yb, refb)
+
+
+def _graded(m, n, decay, seed):
+    k = min(m, n)
+    U = random_orthogonal(m, seed)[:, :k]
+    V = random_orthogonal(n, seed + 1)[:, :k]
+    return U @ np.diag(decay ** np.arange(k)) @ V.T
+
+
+SVD_CASES = [("square16", lambda: np.random.default_rng(0).standard_normal((16, 16)), 8),
+             ("tall", lambda: np.random.default_rng(1).standard_normal((300, 40)), 12),
+             ("wide", lambda: np.random.default_rng(2).standard_normal((40, 300)), 12),
+             ("graded", lambda: _graded(96, 96, 0.8, 3), 64),
+             ("rankdef", lambda: np.random.default_rng(4).standard_normal((64, 5))
+              @ np.random.default_rng(5).standard_normal((5, 70)), 10),
+             ("k>rank", lambda: np.random.default_rng(6).standard_normal((24, 24)), 64),
+             ("tall256", lambda: _graded(512, 256, 0.97, 7), 256)]
+
+
+@pytest.mark.parametrize("name,make,k", SVD_CASES)
+def test_tsvd_matches_oracle_truncate(name, make, k):
+    log("tsvd", name)
+    M = make()
+    U, S = tsvd(M, k)
+    Uo, So = O.truncate(M, k)
+    assert U.shape == Uo.shape
+    np.testing.assert_allclose(S, So, rtol=0, atol=1e-12 * So[0])
+    keep = So > 0
+    assert np.array_equal(S > 0, keep)
+    # vectors: compare where the singular value is separated from its neighbours
+    s = np.concatenate([[np.inf], So, [0.0]])
+    for c in np.nonzero(keep)[0]:
+        gap = min(s[c] - s[c + 1], s[c + 1] - s[c + 2]) / So[0]
+        if gap > 1e-6:
+            np.testing.assert_allclose(U[:, c], Uo[:, c], rtol=0, atol=2e-12 / gap + 1e-11)
+    # properties that hold regardless: orthonormal kept columns, Eckart-Young
+    np.testing.assert_allclose(U[:, keep].T @ U[:, keep], np.eye(int(keep.sum())), atol=1e-12)
+    R = M - U @ (U.T @ M)
+    lam = np.sort(np.linalg.eigvalsh(M @ M.T))[::-1]
+    assert abs(np.sum(R * R) - np.clip(lam[int(keep.sum()):], 0, None).sum()) < 1e-10 * lam[0]
