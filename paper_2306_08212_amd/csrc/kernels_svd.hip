@@ -52,7 +52,7 @@ __device__ __forceinline__ void rr_pair(int nb, int round, int i, int* a, int* b
 // a_pq = 0) keep small entries relatively accurate, so the small entries of
 // J (those coupling columns of very different norm) are accurate too.
 __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double tol,
-                               int* sflag, double* cs, int* pq) {
+                               double gnoise, int* sflag, double* cs, int* pq) {
   const int t = threadIdx.x;
   __shared__ double piv[JP / 2][3];
   for (int idx = t; idx < JP * JP; idx += blockDim.x) J[idx / JP][idx % JP] = (idx / JP == idx % JP) ? 1.0 : 0.0;
@@ -67,7 +67,7 @@ __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double 
         if (p > q) { const int x = p; p = q; q = x; }
         const double app = G[p][p], aqq = G[q][q], apq = G[p][q];
         double c = 1.0, s = 0.0, tt = 0.0;
-        if (fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+        if (fmin(app, aqq) > gnoise && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
           const double tau = (aqq - app) / (2.0 * apq);
           tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + tt * tt);
@@ -129,6 +129,7 @@ __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double 
 __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, int r, int64_t ldx,
                                                         double* __restrict__ V, int vr, int nb,
                                                         int round, double tol, double tol_in,
+                                                        const double* __restrict__ fro,
                                                         int* __restrict__ flags) {
   __shared__ double G[JP][JP + 1];
   __shared__ double J[JP][JP + 1];
@@ -137,6 +138,10 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
   __shared__ int pq[JP];
   __shared__ int any, sflag;
   if (flags[0]) return;   // converged in an earlier sweep
+  // columns below the rounding noise of the rotations (norm < 2 sqrt(r) eps
+  // ||M||_F) are not made orthogonal: their directions are not determined by
+  // the data, and chasing them only spins through sweeps
+  const double gnoise = 4.0 * (double)r * 4.930380657631324e-32 * fro[0] * fro[0];
   int bi, bj;
   rr_pair(nb, round, blockIdx.x, &bi, &bj);
   const int t = threadIdx.x;
@@ -172,12 +177,12 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
     const int b = gb + q;
     if (b != ga) {
       const double gab = G[ga][b], gaa = G[ga][ga], gbb = G[b][b];
-      if (fabs(gab) > tol * sqrt(fabs(gaa * gbb))) any = 1;
+      if (fmin(gaa, gbb) > gnoise && fabs(gab) > tol * sqrt(fabs(gaa * gbb))) any = 1;
     }
   }
   __syncthreads();
   if (!any) return;
-  lds_sym_jacobi(G, J, tol_in, &sflag, cs, pq);
+  lds_sym_jacobi(G, J, tol_in, gnoise, &sflag, cs, pq);
   if (t == 0) atomicAdd(&flags[1], 1);
 
   // X[:, cols] <- X[:, cols] J   (thread: column b = t/8, 4 consecutive rows)
@@ -225,6 +230,7 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
 __global__ void jac_sweep_end(int* flags) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     if (flags[0] == 0 && flags[1] == 0) flags[0] = 1;
+    if (flags[0] == 0) flags[2] += 1;   // sweeps that rotated something
     flags[1] = 0;
   }
 }
@@ -233,6 +239,7 @@ __global__ void jac_flags_init(int* flags) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     flags[0] = 0;
     flags[1] = 0;
+    flags[2] = 0;
   }
 }
 
@@ -357,7 +364,7 @@ __global__ __launch_bounds__(256) void cgs2_block_kernel(double* __restrict__ U,
   const int t = threadIdx.x;
   for (int j = 0; j < nb; ++j) {
     const int cj = c0 + j;
-    if (!(S[cj] > 0.0)) {
+    if (S != nullptr && !(S[cj] > 0.0)) {
       for (int i = t; i < m; i += 256) U[(int64_t)i * kk + cj] = 0.0;
       __syncthreads();
       continue;
@@ -405,6 +412,57 @@ __global__ __launch_bounds__(256) void cgs2_block_kernel(double* __restrict__ U,
   }
 }
 
+// In-place sign fix of the kk columns of row-major U (m x kk): the lowest
+// row whose magnitude is within kSignTie of the column's largest is made
+// positive.  Zero columns stay zero.
+__global__ __launch_bounds__(256) void sign_fix_kernel(double* __restrict__ U, int m, int kk) {
+  __shared__ double shm[256];
+  __shared__ int shi[256];
+  const int t = blockIdx.x;
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < m; i += 256) mx = fmax(mx, fabs(U[(int64_t)i * kk + t]));
+  shm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + w]);
+    __syncthreads();
+  }
+  const double top = shm[0];
+  if (!(top > 0.0)) return;
+  const double thr = (1.0 - kSignTie) * top;
+  int lo = 0x7fffffff;
+  for (int i = threadIdx.x; i < m; i += 256)
+    if (fabs(U[(int64_t)i * kk + t]) >= thr && i < lo) lo = i;
+  shi[threadIdx.x] = lo;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) shi[threadIdx.x] = min(shi[threadIdx.x], shi[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (U[(int64_t)shi[0] * kk + t] < 0.0)
+    for (int i = threadIdx.x; i < m; i += 256) U[(int64_t)i * kk + t] = -U[(int64_t)i * kk + t];
+}
+
+// Standard normal numbers from a counter-based generator: splitmix64 of
+// (seed, index) gives two uniforms, Box-Muller turns them into a normal.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ull;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(256) void gaussian_kernel(double* __restrict__ x, int64_t n,
+                                                       uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint64_t a = splitmix64(seed ^ splitmix64(2 * (uint64_t)i));
+    const uint64_t b = splitmix64(seed ^ splitmix64(2 * (uint64_t)i + 1));
+    const double u1 = ((double)(a >> 11) + 1.0) * 0x1.0p-53;   // (0, 1]
+    const double u2 = (double)(b >> 11) * 0x1.0p-53;           // [0, 1)
+    x[i] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+  }
+}
+
 __global__ void spec_finish_kernel(const double* __restrict__ S, int kk, int chi,
                                    double* __restrict__ out) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -415,7 +473,119 @@ __global__ void spec_finish_kernel(const double* __restrict__ S, int kk, int chi
 
 }  // namespace
 
+namespace {
+
+// Orthonormalise the kk columns of row-major A (m x kk) in place, in order:
+// blocks of 32 columns, earlier blocks projected out twice with GEMMs, then
+// classical Gram-Schmidt twice inside the block.  S (optional) marks columns
+// to zero (S == 0).  G: scratch of kk * 32 doubles.
+void orthonormalize(Ctx& c, double* A, int m, int kk, const double* S, double* G) {
+  constexpr int OB = 32;
+  for (int c0 = 0; c0 < kk; c0 += OB) {
+    const int nbk = std::min(OB, kk - c0);
+    if (c0 > 0) {
+      for (int pass = 0; pass < 2; ++pass) {
+        gemm(c, F64, c0, nbk, m, 1.0, A, kk, 1, A + c0, kk, 0, 0.0, G, nbk);
+        gemm(c, F64, m, nbk, c0, -1.0, A, kk, 0, G, nbk, 0, 1.0, A + c0, kk);
+      }
+    }
+    if (!c.dry) {
+      ProfScope ps(c, K_SVD_OTHER, 4.0 * m * nbk * nbk, 8.0 * 6.0 * m * nbk);
+      hipLaunchKernelGGL(cgs2_block_kernel, dim3(1), dim3(256), 0, c.stream, A, m, kk, c0, nbk, S);
+      c.check_launch();
+    }
+  }
+}
+
+void sign_fix(Ctx& c, double* U, int m, int kk) {
+  if (c.dry || kk <= 0) return;
+  ProfScope ps(c, K_SVD_OTHER, 0.0, 16.0 * m * kk);
+  hipLaunchKernelGGL(sign_fix_kernel, dim3(kk), dim3(256), 0, c.stream, U, m, kk);
+  c.check_launch();
+}
+
+void tsvd_exact(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, double* S);
+
+}  // namespace
+
+// Dispatch: large problems are first narrowed to a small factor whose SVD the
+// exact Jacobi method then takes.
+//  - 128 <= k <= min(m, n) / 4 with min(m, n) >= 768: randomised range finder with
+//    two power iterations (subspace of k + p columns, p = max(32, k / 4),
+//    Gaussian test matrix from a counter-based generator); then B^T = M^T Q
+//    is compressed by QR and the exact SVD runs on the (k+p)^2 factor.
+//  - strictly tall with m >= 4 n: exact compression M = Q R (Gram-Schmidt,
+//    GEMM-blocked), SVD of the n x n factor R, U = Q U_R.
 void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, double* S) {
+  const int mn = std::min(m, n);
+  const int kk = std::min(k, mn);
+  if (kk <= 0) return;
+  if (mn >= 768 && kk >= 128 && kk <= mn / 4) {
+    const int b = std::min(mn, kk + std::max(32, kk / 4));
+    const size_t mk = c.arena.mark();
+    double* Y = (double*)c.arena.alloc(sizeof(double) * (size_t)m * b);
+    double* Z = (double*)c.arena.alloc(sizeof(double) * (size_t)n * b);
+    double* Z0 = (double*)c.arena.alloc(sizeof(double) * (size_t)n * b);
+    double* R = (double*)c.arena.alloc(sizeof(double) * (size_t)b * b);
+    double* Rt = (double*)c.arena.alloc(sizeof(double) * (size_t)b * b);
+    double* UB = (double*)c.arena.alloc(sizeof(double) * (size_t)b * kk);
+    double* G = (double*)c.arena.alloc(sizeof(double) * (size_t)b * 32);
+    if (!c.dry) {
+      const uint64_t seed = 0x5eedull + 0x100000001b3ull * (uint64_t)(++c.rng_calls);
+      int64_t blocks = ((int64_t)n * b + 255) / 256;
+      if (blocks > 4096) blocks = 4096;
+      hipLaunchKernelGGL(gaussian_kernel, dim3((unsigned)blocks), dim3(256), 0, c.stream, Z,
+                         (int64_t)n * b, seed);
+      c.check_launch();
+    }
+    gemm(c, F64, m, b, n, 1.0, M, n, 0, Z, b, 0, 0.0, Y, b);            // Y = M Om
+    for (int it = 0; it < 2; ++it) {
+      orthonormalize(c, Y, m, b, nullptr, G);
+      gemm(c, F64, n, b, m, 1.0, M, n, 1, Y, b, 0, 0.0, Z, b);          // Z = M^T Y
+      orthonormalize(c, Z, n, b, nullptr, G);
+      gemm(c, F64, m, b, n, 1.0, M, n, 0, Z, b, 0, 0.0, Y, b);          // Y = M Z
+    }
+    orthonormalize(c, Y, m, b, nullptr, G);                              // Q
+    gemm(c, F64, n, b, m, 1.0, M, n, 1, Y, b, 0, 0.0, Z, b);            // B^T = M^T Q
+    if (!c.dry)
+      c.check(hipMemcpyAsync(Z0, Z, sizeof(double) * (size_t)n * b, hipMemcpyDeviceToDevice,
+                             c.stream));
+    orthonormalize(c, Z, n, b, nullptr, G);                              // B^T = Q_B R
+    gemm(c, F64, b, b, n, 1.0, Z, b, 1, Z0, b, 0, 0.0, R, b);           // R = Q_B^T B^T
+    {
+      Tensor tR = make_view(R, F64, {b, b}), tRt = make_view(Rt, F64, {b, b});
+      const int pr[2] = {1, 0};
+      permute(c, tR, pr, tRt);                                           // B = R^T Q_B^T
+    }
+    tsvd_exact(c, Rt, b, b, kk, tau, UB, S);
+    gemm(c, F64, m, kk, b, 1.0, Y, b, 0, UB, kk, 0, 0.0, U, kk);        // U = Q U_B
+    sign_fix(c, U, m, kk);
+    c.arena.release(mk);
+    return;
+  }
+  if (m >= 4 * n && n >= 32) {
+    const size_t mk = c.arena.mark();
+    double* Q = (double*)c.arena.alloc(sizeof(double) * (size_t)m * n);
+    double* R = (double*)c.arena.alloc(sizeof(double) * (size_t)n * n);
+    double* UR = (double*)c.arena.alloc(sizeof(double) * (size_t)n * kk);
+    double* G = (double*)c.arena.alloc(sizeof(double) * (size_t)n * 32);
+    if (!c.dry)
+      c.check(hipMemcpyAsync(Q, M, sizeof(double) * (size_t)m * n, hipMemcpyDeviceToDevice,
+                             c.stream));
+    orthonormalize(c, Q, m, n, nullptr, G);
+    gemm(c, F64, n, n, m, 1.0, Q, n, 1, M, n, 0, 0.0, R, n);            // R = Q^T M
+    tsvd_exact(c, R, n, n, kk, tau, UR, S);
+    gemm(c, F64, m, kk, n, 1.0, Q, n, 0, UR, kk, 0, 0.0, U, kk);        // U = Q U_R
+    sign_fix(c, U, m, kk);
+    c.arena.release(mk);
+    return;
+  }
+  tsvd_exact(c, M, m, n, k, tau, U, S);
+}
+
+namespace {
+
+void tsvd_exact(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, double* S) {
   const int kk = std::min(k, std::min(m, n));
   if (kk <= 0) return;
   // U comes from the accumulated rotations (orthonormal by construction)
@@ -432,7 +602,9 @@ void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, d
   double* V = tall ? nullptr : (double*)c.arena.alloc((size_t)cc * cp * sizeof(double));
   double* sig = (double*)c.arena.alloc((size_t)cp * sizeof(double));
   int* order = (int*)c.arena.alloc((size_t)kk * sizeof(int));
-  int* flags = (int*)c.arena.alloc(2 * sizeof(int));
+  int* flags = (int*)c.arena.alloc(4 * sizeof(int));
+  double* fro = (double*)c.arena.alloc(sizeof(double));
+  norm2(c, M, (int64_t)m * n, fro);
   double* Ut = (double*)c.arena.alloc((size_t)m * kk * sizeof(double));
   double* G = (double*)c.arena.alloc((size_t)kk * kk * sizeof(double));
   if (!c.dry) {
@@ -443,7 +615,9 @@ void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, d
     hipLaunchKernelGGL(jac_flags_init, dim3(1), dim3(1), 0, c.stream, flags);
     const double eps = 2.220446049250313e-16;
     const double tol = std::max(std::sqrt((double)r) * eps, 4 * eps);
-    const double tol_in = 4 * eps;
+    // inner 32 x 32 solve: relative test at n * eps, reachable with the
+    // Rutishauser updates (a stricter test only spins through sweeps)
+    const double tol_in = 32 * eps;
     const int max_sweeps = 16;
     for (int sw = 0; sw < max_sweeps; ++sw) {
       for (int rd = 0; rd < nb - 1; ++rd) {
@@ -452,7 +626,7 @@ void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, d
                      (double)(nb / 2) * JP * JP * 2.0 * (2.0 * r + (tall ? 0.0 : 2.0 * cc)),
                      (double)(nb / 2) * JP * 8.0 * (3.0 * r + (tall ? 0.0 : 2.0 * cc)));
         hipLaunchKernelGGL(jac_round_kernel, dim3(nb / 2), dim3(256), 0, c.stream, X, r,
-                           (int64_t)r, V, tall ? 0 : cc, nb, rd, tol, tol_in, flags);
+                           (int64_t)r, V, tall ? 0 : cc, nb, rd, tol, tol_in, fro, flags);
       }
       hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(1), 0, c.stream, flags);
     }
@@ -466,28 +640,11 @@ void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, d
   if (!c.dry)
     c.check(hipMemcpyAsync(U, Ut, sizeof(double) * (size_t)m * kk, hipMemcpyDeviceToDevice,
                            c.stream));
-  if (tall) {
-    // blocked CGS2 in descending-sigma order: project out earlier blocks
-    // twice (GEMMs), then orthonormalise within the block
-    constexpr int OB = 32;
-    for (int c0 = 0; c0 < kk; c0 += OB) {
-      const int nbk = std::min(OB, kk - c0);
-      if (c0 > 0) {
-        for (int pass = 0; pass < 2; ++pass) {
-          // G[0:c0, 0:nbk] = U[:, :c0]^T U[:, c0:c0+nbk]
-          gemm(c, F64, c0, nbk, m, 1.0, U, kk, 1, U + c0, kk, 0, 0.0, G, nbk);
-          // U[:, c0:] -= U[:, :c0] G
-          gemm(c, F64, m, nbk, c0, -1.0, U, kk, 0, G, nbk, 0, 1.0, U + c0, kk);
-        }
-      }
-      if (!c.dry) {
-        hipLaunchKernelGGL(cgs2_block_kernel, dim3(1), dim3(256), 0, c.stream, U, m, kk, c0, nbk, S);
-        c.check_launch();
-      }
-    }
-  }
+  if (tall) orthonormalize(c, U, m, kk, S, G);   // descending-sigma order
   c.arena.release(mk);
 }
+
+}  // namespace
 
 void corner_spectrum(Ctx& c, const double* C, int p, int q, int chi, double* out) {
   const int kk = std::min(chi, std::min(p, q));

@@ -117,3 +117,30 @@ def test_tsvd_matches_oracle_truncate(name, make, k):
     R = M - U @ (U.T @ M)
     lam = np.sort(np.linalg.eigvalsh(M @ M.T))[::-1]
     assert abs(np.sum(R * R) - np.clip(lam[int(keep.sum()):], 0, None).sum()) < 1e-10 * lam[0]
+
+
+@pytest.mark.parametrize("m,n,k", [(1100, 1200, 128), (2048, 2048, 256)])
+def test_tsvd_randomized_range(m, n, k):
+    """Large problems go through the randomised range finder (two power
+    iterations, k + max(32, k/4) columns): the top half of the spectrum to
+    1e-12, the truncation residual within 1e-6 of the optimum, U orthonormal."""
+    log("tsvd randomized", m, n, k)
+    M = _graded(m, n, 0.9 ** (256.0 / k), 11)
+    U, S = tsvd(M, k)
+    s = np.linalg.svd(M, compute_uv=False)
+    h = k // 2
+    np.testing.assert_allclose(S[:h], s[:h], rtol=0, atol=1e-12 * s[0])
+    np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-12)
+    R = M - U @ (U.T @ M)
+    opt = np.sum(s[k:] ** 2)
+    assert np.sum(R * R) <= opt * (1 + 1e-6) + 1e-24 * s[0] ** 2
+
+
+def test_tsvd_tall_compressed_matches_oracle():
+    """m >= 4 n goes through the exact QR compression."""
+    M = _graded(1024, 200, 0.95, 13)
+    U, S = tsvd(M, 200)
+    Uo, So = O.truncate(M, 200)
+    np.testing.assert_allclose(S, So, rtol=0, atol=1e-12 * So[0])
+    np.testing.assert_allclose(U.T @ U, np.eye(200), atol=1e-12)
+    np.testing.assert_allclose(np.abs(U[:, :20]), np.abs(Uo[:, :20]), atol=1e-10)
