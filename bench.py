@@ -84,6 +84,35 @@ def cpu_baseline(d, D, chi, seed=0):
                       f"full-rank environment, FP64 NumPy, {dt:.1f} s; moves/s = 1/(4 t)"}
 
 
+def serve_stream(args):
+    """Serving: independent solves with D uniform in {3..dmax}, chi uniform in
+    [D^2, min(4 D^2, 256)], FP32 chains, a fixed number of iterations each.
+    First all requests at once (closed loop) to find the saturated rate mu,
+    then a seeded Poisson stream at 0.8 mu for latency percentiles."""
+    from paper_2306_08212_amd.serve import GpuBackend, Request, Server, summarize
+    from synth import serving_stream
+    be = GpuBackend()
+
+    def reqs(n, seed, rate):
+        out = []
+        for q in serving_stream(n, seed, rate, d=args.d, D_min=3, D_max=args.serve_dmax):
+            out.append(Request(id=q["id"], d=q["d"], D=q["D"], chi=q["chi"], seed=q["seed"],
+                               t_arrival=q["t_arrival"], max_iters=args.serve_iters,
+                               tol=0.0, precision=1))
+        return out
+
+    n_closed = max(8, args.serve_requests // 2)
+    closed = summarize(Server(be, max_slots=16).run(reqs(n_closed, 7, 0.0)))
+    mu = closed["solves_per_s"] or 1.0
+    log(f"bench: serving closed loop {closed}")
+    rate = 0.8 * mu
+    opened = summarize(Server(be, max_slots=16).run(reqs(args.serve_requests, 8, rate)))
+    log(f"bench: serving open loop at {rate:.2f}/s {opened}")
+    return {"workload": f"D uniform in 3..{args.serve_dmax}, chi uniform in [D^2, 4 D^2], "
+                        f"d={args.d}, {args.serve_iters} iterations each, FP32 chains",
+            "closed_loop": closed, "open_loop_rate_per_s": rate, "open_loop": opened}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +125,11 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=4,
                     help="moves timed again with FP64 chains (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--serve-requests", type=int, default=24,
+                    help="requests in the open-loop serving stream (0 = skip serving)")
+    ap.add_argument("--serve-dmax", type=int, default=3,
+                    help="largest D in the serving stream (D uniform in 3..dmax)")
+    ap.add_argument("--serve-iters", type=int, default=8, help="iterations per served solve")
     ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
 
@@ -167,6 +201,10 @@ def main():
         fp64_mps = args.fp64_steps / (ms64 / 1e3)
     s.close()
 
+    serving = None
+    if args.serve_requests > 0:
+        serving = serve_stream(args)
+
     cpu = None
     if not args.no_cpu:
         log("bench: timing the CPU oracle sample")
@@ -195,6 +233,7 @@ def main():
                        "frac_of_fp32_mfma_peak": fm * moves_per_s / 157.3e12,
                        "gemm_flop_per_move_measured": gemm_flops},
         "fp64_moves_per_s": fp64_mps,
+        "serving": serving,
         "kernel_breakdown": breakdown,
         "cpu_baseline": cpu,
     }

@@ -100,6 +100,13 @@ int ctm_iterate(ctm_solver *s, int n);
  * per iteration (synchronises).  iters_done/delta may be NULL. */
 int ctm_converge(ctm_solver *s, int max_iters, double tol, int *iters_done, double *delta);
 
+/* One full iteration followed by the corner-spectrum change delta, all
+ * enqueued on the stream with no host wait (for schedulers that overlap many
+ * solves); ctm_read_delta then synchronises the stream and returns delta, or
+ * CTM_ENUMERIC if a tensor norm failed. */
+int ctm_iterate_delta(ctm_solver *s);
+int ctm_read_delta(ctm_solver *s, double *delta);
+
 /* Bond energies <h> of the four bond types and the per-site energy
  * e_site = (sum of e_bond) / 2.  h2 is a host d^2 x d^2 row-major operator
  * h[(s1 s2)][(s1' s2')] acting on (left, right) or (top, bottom) sites, or

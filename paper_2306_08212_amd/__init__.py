@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 METHODS = {"standard": STANDARD, "reduced": REDUCED}
 
 EXPORTS = ["ctm_workspace_size", "ctm_init", "ctm_move", "ctm_iterate", "ctm_converge",
-           "ctm_energy", "ctm_get_env", "ctm_set_env", "ctm_moves_done", "ctm_set_precision",
+           "ctm_iterate_delta", "ctm_read_delta", "ctm_energy", "ctm_get_env", "ctm_set_env", "ctm_moves_done", "ctm_set_precision",
            "ctm_profile", "ctm_profile_read", "ctm_destroy",
            "ctm_status_string", "ctm_kernel_gemm", "ctm_kernel_tsvd", "ctm_kernel_tsvd_workspace",
            "ctm_kernel_permute"]
@@ -72,6 +72,10 @@ def load(path: str = LIB_PATH):
     lib.ctm_iterate.restype = I
     lib.ctm_converge.argtypes = [P, I, D, ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.ctm_converge.restype = I
+    lib.ctm_iterate_delta.argtypes = [P]
+    lib.ctm_iterate_delta.restype = I
+    lib.ctm_read_delta.argtypes = [P, ctypes.POINTER(D)]
+    lib.ctm_read_delta.restype = I
     lib.ctm_energy.argtypes = [P, P, ctypes.POINTER(D), ctypes.POINTER(D)]
     lib.ctm_energy.restype = I
     lib.ctm_get_env.argtypes = [P, I, P, ctypes.c_size_t, ctypes.POINTER(I), ctypes.POINTER(I)]
@@ -195,6 +199,15 @@ class Solver:
         st = load().ctm_converge(self.handle, max_iters, tol, ctypes.byref(it), ctypes.byref(dl))
         _check(st, "ctm_converge", ok=(CTM_OK, CTM_ENOTCONV))
         return it.value, dl.value, st == CTM_OK
+
+    def iterate_delta(self):
+        """Enqueue one iteration and its delta; returns at once."""
+        _check(load().ctm_iterate_delta(self.handle), "ctm_iterate_delta")
+
+    def read_delta(self) -> float:
+        dl = ctypes.c_double()
+        _check(load().ctm_read_delta(self.handle, ctypes.byref(dl)), "ctm_read_delta")
+        return dl.value
 
     def energy(self, h2: Optional[np.ndarray] = None):
         e = ctypes.c_double()

@@ -320,6 +320,9 @@ void insert_column(ctm_solver* s, int r) {
 }
 
 void do_move(ctm_solver* s, int r) {
+  // random test matrices of the truncations depend only on their position in
+  // the move, so a move from a given state is reproducible in any precision
+  s->ctx.rng_calls = 0;
   insert_column(s, r);
   insert_column(s, r);
   s->moves++;
@@ -644,6 +647,38 @@ int ctm_converge(ctm_solver* s, int max_iters, double tol, int* iters_done, doub
   const int st = status_from(s);
   if (st != CTM_OK) return st;
   return (dl < tol) ? CTM_OK : CTM_ENOTCONV;
+}
+
+int ctm_iterate_delta(ctm_solver* s) {
+  if (!s) return CTM_EINVAL;
+  Ctx& c = s->ctx;
+  try {
+    if (!s->spec_valid) {
+      corner_spectra(s);
+      s->spec_valid = true;
+    }
+    do_iteration(s);
+    s->spec_cur ^= 1;
+    corner_spectra(s);
+    max_abs_diff(c, s->spec[s->spec_cur], s->spec[s->spec_cur ^ 1], 8 * s->chi, s->scal + 32);
+  } catch (...) {
+    return CTM_EINVAL;
+  }
+  return status_from(s);
+}
+
+int ctm_read_delta(ctm_solver* s, double* delta) {
+  if (!s) return CTM_EINVAL;
+  Ctx& c = s->ctx;
+  double dl = INFINITY;
+  int flag = 0;
+  c.check(hipMemcpyAsync(&dl, s->scal + 32, sizeof(double), hipMemcpyDeviceToHost, c.stream));
+  c.check(hipMemcpyAsync(&flag, c.dev_flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  c.check(hipStreamSynchronize(c.stream));
+  if (delta) *delta = dl;
+  const int st = status_from(s);
+  if (st != CTM_OK) return st;
+  return flag ? CTM_ENUMERIC : CTM_OK;
 }
 
 int ctm_energy(ctm_solver* s, const double* h2, double* e_site, double e_bond[4]) {
