@@ -9,6 +9,8 @@
 //   BF16 : v_mfma_f32_32x32x16_bf16 (bf16 in, fp32 accumulate/out), 128 x 128
 // Ragged edges are zero-filled on the way into LDS; nothing is read or
 // written outside [0,m) x [0,n).
+#include <algorithm>
+
 #include "ctm_internal.h"
 
 namespace ctm {
@@ -22,16 +24,22 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int F64_BM = 64, F64_BN = 64, F64_BK = 16;
 
+// Split-K: blockIdx.z takes K range [z * kchunk, min(K, (z + 1) * kchunk)).
+// With part != nullptr the raw partial products go to part (one M x N slab
+// per (z, batch) pair) and a separate pass sums them in a fixed order.
 __global__ __launch_bounds__(256) void gemm_f64_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda, int ta,
     const double* __restrict__ B, int64_t ldb, int tb, double beta, double* __restrict__ C,
-    int64_t ldc, int64_t sA, int64_t sB, int64_t sC, int tiles_n) {
+    int64_t ldc, int64_t sA, int64_t sB, int64_t sC, int tiles_n, int kchunk,
+    double* __restrict__ part) {
   __shared__ double As[F64_BK][F64_BM + 2];
   __shared__ double Bs[F64_BK][F64_BN + 2];
   const int bz = blockIdx.y;
   A += sA * bz;
   B += sB * bz;
   C += sC * bz;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(K, kbeg + kchunk);
   const int tile = blockIdx.x;
   const int m0 = (tile / tiles_n) * F64_BM, n0 = (tile % tiles_n) * F64_BN;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -40,13 +48,13 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = 0; k0 < K; k0 += F64_BK) {
+  for (int k0 = kbeg; k0 < kend; k0 += F64_BK) {
     for (int e = tid; e < F64_BM * F64_BK; e += 256) {
       int mm, kk;
       if (!ta) { mm = e / F64_BK; kk = e % F64_BK; } else { kk = e / F64_BM; mm = e % F64_BM; }
       const int gm = m0 + mm, gk = k0 + kk;
       double v = 0.0;
-      if (gm < M && gk < K) v = ta ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
+      if (gm < M && gk < kend) v = ta ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
       As[kk][mm] = v;
     }
     for (int e = tid; e < F64_BN * F64_BK; e += 256) {
@@ -54,7 +62,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
       if (!tb) { kk = e / F64_BN; nn = e % F64_BN; } else { nn = e / F64_BK; kk = e % F64_BK; }
       const int gn = n0 + nn, gk = k0 + kk;
       double v = 0.0;
-      if (gn < N && gk < K) v = tb ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
+      if (gn < N && gk < kend) v = tb ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
       Bs[kk][nn] = v;
     }
     __syncthreads();
@@ -80,11 +88,34 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
         const int gm = m0 + wm + i * 16 + (lane >> 4) + 4 * r;
         const int gn = n0 + wn + j * 16 + (lane & 15);
         if (gm < M && gn < N) {
-          double* cp = C + (int64_t)gm * ldc + gn;
-          const double v = alpha * acc[i][j][r];
-          *cp = (beta == 0.0) ? v : v + beta * (*cp);
+          if (part != nullptr) {
+            part[(((int64_t)blockIdx.z * gridDim.y + bz) * M + gm) * N + gn] = acc[i][j][r];
+          } else {
+            double* cp = C + (int64_t)gm * ldc + gn;
+            const double v = alpha * acc[i][j][r];
+            *cp = (beta == 0.0) ? v : v + beta * (*cp);
+          }
         }
       }
+}
+
+// C = alpha * sum_z part[z] + beta * C, summed in z order.
+__global__ __launch_bounds__(256) void gemm_f64_splitk_sum(int M, int N, int batch, int splits,
+                                                           double alpha,
+                                                           const double* __restrict__ part,
+                                                           double beta, double* __restrict__ C,
+                                                           int64_t ldc, int64_t sC) {
+  const int64_t per = (int64_t)M * N, total = per * batch;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    double acc = 0.0;
+    for (int z = 0; z < splits; ++z) acc += part[(int64_t)z * total + e];
+    const int64_t bz = e / per, r = e % per;
+    const int gm = (int)(r / N), gn = (int)(r % N);
+    double* cp = C + sC * bz + (int64_t)gm * ldc + gn;
+    const double v = alpha * acc;
+    *cp = (beta == 0.0) ? v : v + beta * (*cp);
+  }
 }
 
 // ---------------------------------------------------------------- FP32
@@ -249,8 +280,37 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(
 void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A, int64_t lda,
           int ta, const void* B, int64_t ldb, int tb, double beta, void* C, int64_t ldc,
           int batch, int64_t sA, int64_t sB, int64_t sC) {
-  if (c.dry || m <= 0 || n <= 0 || batch <= 0) return;
+  if (m <= 0 || n <= 0 || batch <= 0) return;
   if (k < 0) k = 0;
+  // FP64 grids that cannot fill the chip split K (partials in the arena,
+  // summed in a fixed order by a second pass, so results stay bitwise
+  // reproducible)
+  int splits = 1, kchunk = k;
+  double* part = nullptr;
+  size_t mk = c.arena.mark();
+  if (dtype == F64) {
+    const int64_t tiles = (int64_t)((m + F64_BM - 1) / F64_BM) * ((n + F64_BN - 1) / F64_BN) * batch;
+    const bool have_arena = c.arena.dry || c.arena.base != nullptr;
+    if (have_arena && tiles < 256 && k >= 256) {
+      int64_t want = (512 + tiles - 1) / tiles;
+      want = std::min<int64_t>(want, std::min<int64_t>(32, k / 128));
+      if (want > 1) {
+        kchunk = (int)(((k + want - 1) / want + F64_BK - 1) / F64_BK) * F64_BK;
+        splits = (k + kchunk - 1) / kchunk;
+      }
+    }
+    if (splits > 1) {
+      part = (double*)c.arena.alloc(sizeof(double) * (size_t)splits * batch * m * n);
+      if (part == nullptr && !c.dry) {   // no room: one pass over K
+        splits = 1;
+        kchunk = k;
+      }
+    }
+  }
+  if (c.dry) {
+    c.arena.release(mk);
+    return;
+  }
   // k == 0 needs no special case: the K loop is empty and C = beta * C.
   const double es = dtype == F64 ? 8.0 : (dtype == F32 ? 4.0 : 2.0);
   const double eo = dtype == F64 ? 8.0 : 4.0;
@@ -259,10 +319,16 @@ void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A, i
                ((double)m * k + (double)k * n) * es * batch + (double)m * n * eo * batch);
   if (dtype == F64) {
     const int tm = (m + F64_BM - 1) / F64_BM, tn = (n + F64_BN - 1) / F64_BN;
-    dim3 grid(tm * tn, batch);
+    dim3 grid(tm * tn, batch, splits);
     hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, c.stream, m, n, k, alpha,
                        (const double*)A, lda, ta, (const double*)B, ldb, tb, beta, (double*)C,
-                       ldc, sA, sB, sC, tn);
+                       ldc, sA, sB, sC, tn, kchunk, part);
+    if (splits > 1) {
+      int64_t blocks = ((int64_t)m * n * batch + 255) / 256;
+      if (blocks > 4096) blocks = 4096;
+      hipLaunchKernelGGL(gemm_f64_splitk_sum, dim3((unsigned)blocks), dim3(256), 0, c.stream, m, n,
+                         batch, splits, alpha, part, beta, (double*)C, ldc, sC);
+    }
   } else if (dtype == F32) {
     const int tm = (m + F32_BM - 1) / F32_BM, tn = (n + F32_BN - 1) / F32_BN;
     dim3 grid(tm * tn, batch);
@@ -277,6 +343,7 @@ void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A, i
                        (float*)C, ldc, sA, sB, sC, tn);
   }
   c.check_launch();
+  c.arena.release(mk);
 }
 
 }  // namespace ctm

@@ -2,32 +2,43 @@
 //
 // The isometries of the move are the top-k left singular vectors of a
 // reshaped sub-network (standard isometry, the split isometries v^1, v^2 and
-// the helper isometries v_l, v_r).  They are computed here with a one-sided
-// (Hestenes) block Jacobi method:
+// the helper isometries v_l, v_r).  They are computed with a QR-preconditioned
+// one-sided (Hestenes) block Jacobi method:
 //
-//   X (r x c, column-major, r >= c) is orthogonalised by plane rotations
-//   applied from the right, X <- X J, until every pair of columns is
-//   orthogonal to tol relative to their norms.  Then X = U Sigma: the
-//   singular values are the column norms and the left singular vectors the
-//   normalised columns.  If M is wide (m < n) the method runs on M^T and the
-//   accumulated rotations V are the left singular vectors of M.
+//   For M (m x n, m >= n) the columns are ordered by decreasing norm and
+//   orthonormalised (M P = Q R, blocked classical Gram-Schmidt applied
+//   twice).  X = R^T (n x n) is then orthogonalised by plane rotations from
+//   the right, X <- X J, until every pair of columns is orthogonal.  With
+//   R^T J = W Sigma we have M P = (Q J) Sigma W^T, so U = Q J: the singular
+//   values are the column norms of X and the left singular vectors are the
+//   accumulated rotations mapped through Q (orthonormal by construction).
+//   The triangular factor of a norm-ordered QR has rows of decreasing size,
+//   which makes its transpose nearly column-orthogonal: the Jacobi sweeps
+//   then converge in a few sweeps even for strongly graded spectra, where on
+//   M itself they crawl.  A wide M (m < n) is first reduced to the square
+//   L = M Q_1 from the QR of M^T, which has the same left singular vectors.
+//
+// Stopping test for a pair of columns a, b with Gram entries g_aa, g_bb, g_ab:
+// no rotation if either column is below the rounding noise of the rotations
+// (g < 4 r eps^2 ||M||_F^2), if |g_ab| <= r eps sqrt(g_aa g_bb) (orthogonal to
+// working accuracy), or if |g_ab| <= 4 eps ||M||_F sqrt(max(g_aa, g_bb)): the
+// component of one column along the other is then below eps ||M||_F, the
+// absolute accuracy any backward-stable SVD (and LAPACK's) delivers.  Without
+// that absolute floor, columns of very small norm chase orthogonality they
+// cannot reach and the sweeps never end.
 //
 // Columns are grouped in blocks of 16; one workgroup takes a pair of blocks
-// (32 columns), forms their 32 x 32 Gram matrix, diagonalises it with cyclic
-// Jacobi in LDS, and applies the resulting rotation to the 32 columns of X
-// (and of V).  Block pairs follow a round-robin tournament, so the pairs of
-// one round are disjoint and run as one launch.  A device flag ends the
-// sweeps once a full sweep applied no rotation.
+// (32 columns), forms their 32 x 32 Gram matrix, diagonalises it with at most
+// two cyclic Jacobi sweeps in LDS (the outer sweeps finish the job), and
+// applies the resulting rotation to the 32 columns of X and of J.  Block
+// pairs follow a round-robin tournament, so the pairs of one round are
+// disjoint and run as one launch.  A device flag ends the sweeps once a full
+// sweep applied no rotation.
 //
 // Afterwards the columns are ranked by norm (ties by index), the top kk are
-// written out, columns with sigma <= tau * sigma_0 are zeroed and every kept
-// column is sign-fixed: among the rows whose magnitude is within 1e-8
-// (relative) of the largest, the lowest is made positive.  Rotations built
-// from Gram entries leave columns of small sigma orthogonal to the large ones
-// only to about eps * sigma_0 / sigma_j.  So U is taken from the accumulated
-// rotations whenever m <= n, and for strictly tall M blocked classical
-// Gram-Schmidt applied twice, in descending-sigma order, restores
-// orthonormality.
+// kept, columns with sigma <= tau * sigma_0 are zeroed and every kept column
+// of U is sign-fixed: among the rows whose magnitude is within 1e-8
+// (relative) of the largest, the lowest is made positive.
 #include <cmath>
 
 #include "ctm_internal.h"
@@ -46,18 +57,25 @@ __device__ __forceinline__ void rr_pair(int nb, int round, int i, int* a, int* b
   *b = pos(nb - 1 - i);
 }
 
+// Rotation test for a column pair (see the file comment): thr = 4 eps ||M||_F.
+__device__ __forceinline__ bool needs_rotation(double app, double aqq, double apq, double tol,
+                                               double gnoise, double thr) {
+  return fmin(app, aqq) > gnoise && fabs(apq) > tol * sqrt(fabs(app * aqq)) &&
+         fabs(apq) > thr * sqrt(fmax(app, aqq));
+}
+
 // in-LDS cyclic Jacobi on the symmetric positive semi-definite 32 x 32 Gram
-// matrix G; J accumulates the rotations.  Relative stopping test and
+// matrix G, at most max_sweeps sweeps; J accumulates the rotations.
 // Rutishauser's update of the pivot entries (a_pp - t a_pq, a_qq + t a_pq,
-// a_pq = 0) keep small entries relatively accurate, so the small entries of
-// J (those coupling columns of very different norm) are accurate too.
+// a_pq = 0) keeps small entries relatively accurate.
 __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double tol,
-                               double gnoise, int* sflag, double* cs, int* pq) {
+                               double gnoise, double thr, int max_sweeps, int* sflag,
+                               double* cs, int* pq) {
   const int t = threadIdx.x;
   __shared__ double piv[JP / 2][3];
   for (int idx = t; idx < JP * JP; idx += blockDim.x) J[idx / JP][idx % JP] = (idx / JP == idx % JP) ? 1.0 : 0.0;
   __syncthreads();
-  for (int sweep = 0; sweep < 30; ++sweep) {
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (t == 0) *sflag = 0;
     __syncthreads();
     for (int round = 0; round < JP - 1; ++round) {
@@ -67,7 +85,7 @@ __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double 
         if (p > q) { const int x = p; p = q; q = x; }
         const double app = G[p][p], aqq = G[q][q], apq = G[p][q];
         double c = 1.0, s = 0.0, tt = 0.0;
-        if (fmin(app, aqq) > gnoise && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+        if (needs_rotation(app, aqq, apq, tol, gnoise, thr)) {
           const double tau = (aqq - app) / (2.0 * apq);
           tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
           c = 1.0 / sqrt(1.0 + tt * tt);
@@ -125,10 +143,12 @@ __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double 
   }
 }
 
-// X: r rows, ld = ldx, column-major.  V: vr rows (0 = none), ld = vr.
+// One round of the block tournament.  X: r rows, ld = ldx, column-major.
+// V: vr rows (0 = none), ld = vr.  fro: ||X||_F on the device.
 __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, int r, int64_t ldx,
                                                         double* __restrict__ V, int vr, int nb,
                                                         int round, double tol, double tol_in,
+                                                        int inner_sweeps,
                                                         const double* __restrict__ fro,
                                                         int* __restrict__ flags) {
   __shared__ double G[JP][JP + 1];
@@ -142,6 +162,7 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
   // ||M||_F) are not made orthogonal: their directions are not determined by
   // the data, and chasing them only spins through sweeps
   const double gnoise = 4.0 * (double)r * 4.930380657631324e-32 * fro[0] * fro[0];
+  const double thr = 4.0 * 2.220446049250313e-16 * fro[0];
   int bi, bj;
   rr_pair(nb, round, blockIdx.x, &bi, &bj);
   const int t = threadIdx.x;
@@ -177,12 +198,12 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
     const int b = gb + q;
     if (b != ga) {
       const double gab = G[ga][b], gaa = G[ga][ga], gbb = G[b][b];
-      if (fmin(gaa, gbb) > gnoise && fabs(gab) > tol * sqrt(fabs(gaa * gbb))) any = 1;
+      if (needs_rotation(gaa, gbb, gab, tol, gnoise, thr)) any = 1;
     }
   }
   __syncthreads();
   if (!any) return;
-  lds_sym_jacobi(G, J, tol_in, gnoise, &sflag, cs, pq);
+  lds_sym_jacobi(G, J, tol_in, gnoise, thr, inner_sweeps, &sflag, cs, pq);
   if (t == 0) atomicAdd(&flags[1], 1);
 
   // X[:, cols] <- X[:, cols] J   (thread: column b = t/8, 4 consecutive rows)
@@ -243,28 +264,50 @@ __global__ void jac_flags_init(int* flags) {
   }
 }
 
-// X (col-major, r x cp) from row-major M (m x n).  transpose: X = M (m >= n),
-// else X = M^T.  Padded columns are zero.  V = identity on c columns.
-__global__ __launch_bounds__(256) void jac_prep_kernel(const double* __restrict__ M, int m, int n,
-                                                       int tall, double* __restrict__ X, int r,
-                                                       int cp, double* __restrict__ V, int vr) {
-  const int64_t total = (int64_t)r * cp;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-    const int j = (int)(e / r), i = (int)(e % r);
-    double v = 0.0;
-    if (tall) {
-      if (j < n) v = M[(int64_t)i * n + j];   // X[:, j] = column j of M
-    } else {
-      if (j < m) v = M[(int64_t)j * n + i];   // X[:, j] = row j of M
-    }
-    X[e] = v;
+// V (col-major, vr x cp) = identity on the first vr columns, zero beyond.
+__global__ __launch_bounds__(256) void eye_kernel(double* __restrict__ V, int vr, int cp) {
+  const int64_t tv = (int64_t)vr * cp;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tv; e += (int64_t)gridDim.x * 256) {
+    const int j = (int)(e / vr), i = (int)(e % vr);
+    V[e] = (i == j) ? 1.0 : 0.0;
   }
-  if (V != nullptr) {
-    const int64_t tv = (int64_t)vr * cp;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tv; e += (int64_t)gridDim.x * 256) {
-      const int j = (int)(e / vr), i = (int)(e % vr);
-      V[e] = (i == j) ? 1.0 : 0.0;
-    }
+}
+
+// Column sums of squares of row-major M (m x n) over row chunks of `rows`
+// rows: part[chunk * n + j].  Fixed summation order (deterministic).
+__global__ __launch_bounds__(256) void rm_colsq_kernel(const double* __restrict__ M, int m, int n,
+                                                       int rows, double* __restrict__ part) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  const int i0 = blockIdx.y * rows, i1 = min(m, i0 + rows);
+  double s = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    const double v = M[(int64_t)i * n + j];
+    s += v * v;
+  }
+  part[(int64_t)blockIdx.y * n + j] = s;
+}
+
+__global__ __launch_bounds__(256) void rm_colnorm_kernel(const double* __restrict__ part,
+                                                         int chunks, int n,
+                                                         double* __restrict__ sig) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int q = 0; q < chunks; ++q) s += part[(int64_t)q * n + j];
+  sig[j] = sqrt(s);
+}
+
+// Q[:, t] = M[:, order[t]] (row-major m x n).
+__global__ __launch_bounds__(256) void gather_cols_kernel(const double* __restrict__ M, int m,
+                                                          int n, const int* __restrict__ order,
+                                                          double* __restrict__ Q) {
+  const int64_t total = (int64_t)m * n;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / n;
+    const int t = (int)(e % n);
+    Q[e] = M[i * n + order[t]];
   }
 }
 
@@ -301,70 +344,44 @@ __global__ __launch_bounds__(256) void jac_rank_kernel(const double* __restrict_
   if (rank < kk) order[rank] = j;
 }
 
-// U[:, t] (row-major m x kk) and S[t]; one workgroup per output column.
-__global__ __launch_bounds__(256) void jac_output_kernel(const double* __restrict__ X, int r,
-                                                         const double* __restrict__ V, int vr,
-                                                         const double* __restrict__ sig,
-                                                         const int* __restrict__ order, int m,
-                                                         int kk, double tau,
-                                                         double* __restrict__ U,
-                                                         double* __restrict__ S) {
-  __shared__ double shm[256];
-  __shared__ int shi[256];
-  const int t = blockIdx.x;
-  const int j = order[t];
+// Uj[:, t] (row-major vr x kk) = column order[t] of the accumulated
+// rotations V (col-major, vr rows), S[t] its singular value; columns with
+// sigma <= tau * sigma_0 (or not finite) are zero with S = 0.
+__global__ __launch_bounds__(256) void jac_pick_kernel(const double* __restrict__ V, int vr,
+                                                       const double* __restrict__ sig,
+                                                       const int* __restrict__ order, int kk,
+                                                       double tau, double* __restrict__ Uj,
+                                                       double* __restrict__ S) {
+  const int64_t total = (int64_t)vr * kk;
   const double s0 = sig[order[0]];
-  const double sj = sig[j];
-  const bool keep = (s0 > 0.0) && (sj > tau * s0) && isfinite(sj);
-  // source column: normalised X column (tall) or V column (wide)
-  auto src = [&](int i) -> double {
-    if (V != nullptr) return V[(int64_t)j * vr + i];
-    return X[(int64_t)j * r + i] / sj;
-  };
-  if (!keep) {
-    for (int i = threadIdx.x; i < m; i += 256) U[(int64_t)i * kk + t] = 0.0;
-    if (threadIdx.x == 0) S[t] = 0.0;
-    return;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int i = (int)(e / kk), t = (int)(e % kk);
+    const int j = order[t];
+    const double sj = sig[j];
+    const bool keep = (s0 > 0.0) && (sj > tau * s0) && isfinite(sj);
+    Uj[e] = keep ? V[(int64_t)j * vr + i] : 0.0;
+    if (i == 0) S[t] = keep ? sj : 0.0;
   }
-  // largest magnitude
-  double mx = 0.0;
-  for (int i = threadIdx.x; i < m; i += 256) mx = fmax(mx, fabs(src(i)));
-  shm[threadIdx.x] = mx;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) shm[threadIdx.x] = fmax(shm[threadIdx.x], shm[threadIdx.x + w]);
-    __syncthreads();
-  }
-  const double thr = (1.0 - kSignTie) * shm[0];
-  __syncthreads();
-  // lowest row within the tie band
-  int lo = 0x7fffffff;
-  for (int i = threadIdx.x; i < m; i += 256)
-    if (fabs(src(i)) >= thr && i < lo) lo = i;
-  shi[threadIdx.x] = lo;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) shi[threadIdx.x] = min(shi[threadIdx.x], shi[threadIdx.x + w]);
-    __syncthreads();
-  }
-  const double sgn = src(shi[0]) < 0.0 ? -1.0 : 1.0;
-  for (int i = threadIdx.x; i < m; i += 256) U[(int64_t)i * kk + t] = sgn * src(i);
-  if (threadIdx.x == 0) S[t] = sj;
 }
 
 // Orthonormalise columns [c0, c0 + nb) of the row-major m x kk matrix U in
 // place, in order, by classical Gram-Schmidt applied twice within the block
-// (earlier blocks are projected out beforehand with GEMMs).  Columns whose
-// singular value was cut (S == 0) stay zero.
+// (earlier blocks are projected out beforehand with GEMMs).  A column whose
+// residual on the first visit is at most 1e-13 of its original norm nrm0, or
+// which on the second visit (final = 1) loses more than half of its unit
+// length again, is numerically dependent on the earlier ones: it is set to
+// zero (and marked in dead[] on the first visit).
 __global__ __launch_bounds__(256) void cgs2_block_kernel(double* __restrict__ U, int m, int kk,
                                                          int c0, int nb,
-                                                         const double* __restrict__ S) {
+                                                         const double* __restrict__ nrm0,
+                                                         int* __restrict__ dead, int final) {
   __shared__ double red[32][257];
   __shared__ double coef[32];
   const int t = threadIdx.x;
   for (int j = 0; j < nb; ++j) {
     const int cj = c0 + j;
-    if (S != nullptr && !(S[cj] > 0.0)) {
+    if (final && dead[cj]) {
       for (int i = t; i < m; i += 256) U[(int64_t)i * kk + cj] = 0.0;
       __syncthreads();
       continue;
@@ -403,7 +420,14 @@ __global__ __launch_bounds__(256) void cgs2_block_kernel(double* __restrict__ U,
     if (t == 0) {
       double sacc = 0.0;
       for (int q = 0; q < 256; ++q) sacc += red[0][q];
-      coef[0] = sacc > 0.0 ? 1.0 / sqrt(sacc) : 0.0;
+      const double nr = sqrt(sacc);
+      // first visit: residual at rounding level of the original column;
+      // second visit (unit norm on entry): more than half the length lost
+      // to the earlier columns means the first visit normalised rounding
+      // noise, so the column is dependent to working precision
+      const bool dep = final ? !(nr > 0.5) : !(nr > 1e-13 * nrm0[cj]);
+      if (!final) dead[cj] = dep ? 1 : 0;
+      coef[0] = dep ? 0.0 : 1.0 / nr;
     }
     __syncthreads();
     const double inv = coef[0];
@@ -475,26 +499,48 @@ __global__ void spec_finish_kernel(const double* __restrict__ S, int kk, int chi
 
 namespace {
 
-// Orthonormalise the kk columns of row-major A (m x kk) in place, in order:
-// blocks of 32 columns, earlier blocks projected out twice with GEMMs, then
-// classical Gram-Schmidt twice inside the block.  S (optional) marks columns
-// to zero (S == 0).  G: scratch of kk * 32 doubles.
-void orthonormalize(Ctx& c, double* A, int m, int kk, const double* S, double* G) {
+// Orthonormalise the kk columns of row-major A (m x kk) in place, in order,
+// by block classical Gram-Schmidt applied twice (BCGS2): for each block of 32
+// columns, project out the earlier blocks (one GEMM pair), orthonormalise
+// inside the block (classical Gram-Schmidt twice), and repeat both steps.
+// The second projection comes after the first in-block normalisation, so a
+// nearly dependent column, which shrinks to a small residual inside the
+// block, is still made orthogonal to the earlier blocks.  Columns dependent
+// to working precision come out as zero columns: the nonzero columns are
+// orthonormal and span the columns of A up to rounding.
+void orthonormalize(Ctx& c, double* A, int m, int kk) {
   constexpr int OB = 32;
+  const size_t mk = c.arena.mark();
+  const int rows = 64;
+  const int chunks = (m + rows - 1) / rows;
+  double* part = (double*)c.arena.alloc(sizeof(double) * (size_t)chunks * kk);
+  double* nrm0 = (double*)c.arena.alloc(sizeof(double) * (size_t)kk);
+  int* dead = (int*)c.arena.alloc(sizeof(int) * (size_t)kk);
+  double* G = (double*)c.arena.alloc(sizeof(double) * (size_t)kk * OB);
+  if (!c.dry) {
+    ProfScope ps(c, K_SVD_OTHER, 0.0, 8.0 * (double)m * kk);
+    hipLaunchKernelGGL(rm_colsq_kernel, dim3((kk + 255) / 256, chunks), dim3(256), 0, c.stream, A,
+                       m, kk, rows, part);
+    hipLaunchKernelGGL(rm_colnorm_kernel, dim3((kk + 255) / 256), dim3(256), 0, c.stream, part,
+                       chunks, kk, nrm0);
+    c.check_launch();
+  }
   for (int c0 = 0; c0 < kk; c0 += OB) {
     const int nbk = std::min(OB, kk - c0);
-    if (c0 > 0) {
-      for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < 2; ++pass) {
+      if (c0 > 0) {
         gemm(c, F64, c0, nbk, m, 1.0, A, kk, 1, A + c0, kk, 0, 0.0, G, nbk);
         gemm(c, F64, m, nbk, c0, -1.0, A, kk, 0, G, nbk, 0, 1.0, A + c0, kk);
       }
-    }
-    if (!c.dry) {
-      ProfScope ps(c, K_SVD_OTHER, 4.0 * m * nbk * nbk, 8.0 * 6.0 * m * nbk);
-      hipLaunchKernelGGL(cgs2_block_kernel, dim3(1), dim3(256), 0, c.stream, A, m, kk, c0, nbk, S);
-      c.check_launch();
+      if (!c.dry) {
+        ProfScope ps(c, K_SVD_OTHER, 4.0 * m * nbk * nbk, 8.0 * 6.0 * m * nbk);
+        hipLaunchKernelGGL(cgs2_block_kernel, dim3(1), dim3(256), 0, c.stream, A, m, kk, c0, nbk,
+                           nrm0, dead, pass);
+        c.check_launch();
+      }
     }
   }
+  c.arena.release(mk);
 }
 
 void sign_fix(Ctx& c, double* U, int m, int kk) {
@@ -504,18 +550,125 @@ void sign_fix(Ctx& c, double* U, int m, int kk) {
   c.check_launch();
 }
 
-void tsvd_exact(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, double* S);
+unsigned grid_for(int64_t n, int64_t cap) {
+  int64_t b = (n + 255) / 256;
+  if (b < 1) b = 1;
+  return (unsigned)(b > cap ? cap : b);
+}
+
+// Q = orthonormalised columns of row-major A (m x n), taken in order of
+// decreasing column norm (ties by index): A P = Q R.
+void orth_sorted(Ctx& c, const double* A, int m, int n, double* Q) {
+  const size_t mk = c.arena.mark();
+  const int rows = 64;
+  const int chunks = (m + rows - 1) / rows;
+  double* part = (double*)c.arena.alloc(sizeof(double) * (size_t)chunks * n);
+  double* sig = (double*)c.arena.alloc(sizeof(double) * (size_t)n);
+  int* order = (int*)c.arena.alloc(sizeof(int) * (size_t)n);
+  if (!c.dry) {
+    ProfScope ps(c, K_SVD_OTHER, 0.0, 16.0 * (double)m * n);
+    hipLaunchKernelGGL(rm_colsq_kernel, dim3((n + 255) / 256, chunks), dim3(256), 0, c.stream, A,
+                       m, n, rows, part);
+    hipLaunchKernelGGL(rm_colnorm_kernel, dim3((n + 255) / 256), dim3(256), 0, c.stream, part,
+                       chunks, n, sig);
+    hipLaunchKernelGGL(jac_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, c.stream, sig, n, n,
+                       order);
+    hipLaunchKernelGGL(gather_cols_kernel, dim3(grid_for((int64_t)m * n, 8192)), dim3(256), 0,
+                       c.stream, A, m, n, order, Q);
+    c.check_launch();
+  }
+  orthonormalize(c, Q, m, n);
+  c.arena.release(mk);
+}
+
+// Truncated SVD of row-major M (m x n, m >= n): U (m x kk), S (kk).
+void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, double* S) {
+  const int kk = std::min(k, n);
+  if (kk <= 0) return;
+  const int r = n;                  // X = R^T is n x n
+  int nb = (n + JW - 1) / JW;
+  if (nb < 2) nb = 2;
+  if (nb & 1) ++nb;
+  const int cp = nb * JW;
+  const size_t mk = c.arena.mark();
+  double* Q = (double*)c.arena.alloc(sizeof(double) * (size_t)m * n);
+  double* X = (double*)c.arena.alloc(sizeof(double) * (size_t)r * cp);
+  double* V = (double*)c.arena.alloc(sizeof(double) * (size_t)n * cp);
+  double* sig = (double*)c.arena.alloc(sizeof(double) * (size_t)cp);
+  int* order = (int*)c.arena.alloc(sizeof(int) * (size_t)kk);
+  int* flags = (int*)c.arena.alloc(4 * sizeof(int));
+  double* fro = (double*)c.arena.alloc(sizeof(double));
+  double* Uj = (double*)c.arena.alloc(sizeof(double) * (size_t)n * kk);
+  orth_sorted(c, M, m, n, Q);
+  // X (column-major, n rows) = R^T = M^T Q, i.e. row-major Q^T M
+  gemm(c, F64, n, n, m, 1.0, Q, n, 1, M, n, 0, 0.0, X, n);
+  if (cp > n) fill(c, X + (size_t)n * n, F64, (int64_t)(cp - n) * n, 0.0);
+  norm2(c, X, (int64_t)n * n, fro);
+  if (!c.dry) {
+    hipLaunchKernelGGL(eye_kernel, dim3(grid_for((int64_t)n * cp, 4096)), dim3(256), 0, c.stream,
+                       V, n, cp);
+    hipLaunchKernelGGL(jac_flags_init, dim3(1), dim3(1), 0, c.stream, flags);
+    const double eps = 2.220446049250313e-16;
+    const double tol = std::max((double)r, 4.0) * eps;
+    // inner test strictly below the outer one, so a block the inner solve
+    // leaves converged also passes the outer test
+    const double tol_in = std::min(32.0, 0.5 * std::max((double)r, 4.0)) * eps;
+    const int inner_sweeps = 2;
+    const int max_sweeps = 14;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+      for (int rd = 0; rd < nb - 1; ++rd) {
+        // work of one round if every pair rotates: Gram + update of X and V
+        ProfScope ps(c, K_SVD_ROUND, (double)(nb / 2) * JP * JP * 2.0 * (2.0 * r + 2.0 * n),
+                     (double)(nb / 2) * JP * 8.0 * (3.0 * r + 2.0 * n));
+        hipLaunchKernelGGL(jac_round_kernel, dim3(nb / 2), dim3(256), 0, c.stream, X, r,
+                           (int64_t)r, V, n, nb, rd, tol, tol_in, inner_sweeps, fro, flags);
+      }
+      hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(1), 0, c.stream, flags);
+    }
+    ProfScope ps(c, K_SVD_OTHER, 0.0, 8.0 * (double)r * cp + 16.0 * (double)n * kk);
+    hipLaunchKernelGGL(jac_colnorm_kernel, dim3(cp), dim3(256), 0, c.stream, X, r, cp, sig);
+    hipLaunchKernelGGL(jac_rank_kernel, dim3((cp + 255) / 256), dim3(256), 0, c.stream, sig, cp,
+                       kk, order);
+    hipLaunchKernelGGL(jac_pick_kernel, dim3(grid_for((int64_t)n * kk, 4096)), dim3(256), 0,
+                       c.stream, V, n, sig, order, kk, tau, Uj, S);
+    c.check_launch();
+  }
+  gemm(c, F64, m, kk, n, 1.0, Q, n, 0, Uj, kk, 0, 0.0, U, kk);          // U = Q J
+  sign_fix(c, U, m, kk);
+  c.arena.release(mk);
+}
+
+// Left singular vectors of a wide M (m < n): M^T P = Q1 R1 gives
+// M = P R1^T Q1^T, so L = M Q1 (m x m) has the left singular vectors and
+// singular values of M.
+void tsvd_wide(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, double* S) {
+  const size_t mk = c.arena.mark();
+  double* MT = (double*)c.arena.alloc(sizeof(double) * (size_t)m * n);
+  double* Q1 = (double*)c.arena.alloc(sizeof(double) * (size_t)n * m);
+  double* L = (double*)c.arena.alloc(sizeof(double) * (size_t)m * m);
+  {
+    Tensor tM = make_view((void*)M, F64, {m, n}), tT = make_view(MT, F64, {n, m});
+    const int pr[2] = {1, 0};
+    permute(c, tM, pr, tT);
+  }
+  orth_sorted(c, MT, n, m, Q1);
+  gemm(c, F64, m, m, n, 1.0, M, n, 0, Q1, m, 0, 0.0, L, m);             // L = M Q1
+  tsvd_core(c, L, m, m, k, tau, U, S);
+  c.arena.release(mk);
+}
 
 }  // namespace
 
 // Dispatch: large problems are first narrowed to a small factor whose SVD the
-// exact Jacobi method then takes.
-//  - 128 <= k <= min(m, n) / 4 with min(m, n) >= 768: randomised range finder with
-//    two power iterations (subspace of k + p columns, p = max(32, k / 4),
-//    Gaussian test matrix from a counter-based generator); then B^T = M^T Q
-//    is compressed by QR and the exact SVD runs on the (k+p)^2 factor.
-//  - strictly tall with m >= 4 n: exact compression M = Q R (Gram-Schmidt,
-//    GEMM-blocked), SVD of the n x n factor R, U = Q U_R.
+// preconditioned Jacobi method then takes.
+//  - 128 <= k <= min(m, n) / 4 with min(m, n) >= 768: randomised range finder
+//    with two power iterations (subspace of b = k + p columns,
+//    p = max(32, k / 4), Gaussian test matrix from a counter-based generator);
+//    with Y = Q the range basis, B = Q^T M is wide and B^T = M^T Q; then
+//    L = B Q_B from the QR of B^T is b x b with the left singular vectors of
+//    B, and U = Q U_L.
+//  - m >= n: QR-preconditioned Jacobi on M.
+//  - m < n: reduction to the square L = M Q_1 first.
 void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, double* S) {
   const int mn = std::min(m, n);
   const int kk = std::min(k, mn);
@@ -525,126 +678,37 @@ void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, d
     const size_t mk = c.arena.mark();
     double* Y = (double*)c.arena.alloc(sizeof(double) * (size_t)m * b);
     double* Z = (double*)c.arena.alloc(sizeof(double) * (size_t)n * b);
-    double* Z0 = (double*)c.arena.alloc(sizeof(double) * (size_t)n * b);
-    double* R = (double*)c.arena.alloc(sizeof(double) * (size_t)b * b);
-    double* Rt = (double*)c.arena.alloc(sizeof(double) * (size_t)b * b);
-    double* UB = (double*)c.arena.alloc(sizeof(double) * (size_t)b * kk);
-    double* G = (double*)c.arena.alloc(sizeof(double) * (size_t)b * 32);
+    double* QB = (double*)c.arena.alloc(sizeof(double) * (size_t)n * b);
+    double* L = (double*)c.arena.alloc(sizeof(double) * (size_t)b * b);
+    double* UL = (double*)c.arena.alloc(sizeof(double) * (size_t)b * kk);
     if (!c.dry) {
       const uint64_t seed = 0x5eedull + 0x100000001b3ull * (uint64_t)(++c.rng_calls);
-      int64_t blocks = ((int64_t)n * b + 255) / 256;
-      if (blocks > 4096) blocks = 4096;
-      hipLaunchKernelGGL(gaussian_kernel, dim3((unsigned)blocks), dim3(256), 0, c.stream, Z,
-                         (int64_t)n * b, seed);
+      hipLaunchKernelGGL(gaussian_kernel, dim3(grid_for((int64_t)n * b, 4096)), dim3(256), 0,
+                         c.stream, Z, (int64_t)n * b, seed);
       c.check_launch();
     }
     gemm(c, F64, m, b, n, 1.0, M, n, 0, Z, b, 0, 0.0, Y, b);            // Y = M Om
     for (int it = 0; it < 2; ++it) {
-      orthonormalize(c, Y, m, b, nullptr, G);
+      orthonormalize(c, Y, m, b);
       gemm(c, F64, n, b, m, 1.0, M, n, 1, Y, b, 0, 0.0, Z, b);          // Z = M^T Y
-      orthonormalize(c, Z, n, b, nullptr, G);
+      orthonormalize(c, Z, n, b);
       gemm(c, F64, m, b, n, 1.0, M, n, 0, Z, b, 0, 0.0, Y, b);          // Y = M Z
     }
-    orthonormalize(c, Y, m, b, nullptr, G);                              // Q
+    orthonormalize(c, Y, m, b);                              // Q
     gemm(c, F64, n, b, m, 1.0, M, n, 1, Y, b, 0, 0.0, Z, b);            // B^T = M^T Q
-    if (!c.dry)
-      c.check(hipMemcpyAsync(Z0, Z, sizeof(double) * (size_t)n * b, hipMemcpyDeviceToDevice,
-                             c.stream));
-    orthonormalize(c, Z, n, b, nullptr, G);                              // B^T = Q_B R
-    gemm(c, F64, b, b, n, 1.0, Z, b, 1, Z0, b, 0, 0.0, R, b);           // R = Q_B^T B^T
-    {
-      Tensor tR = make_view(R, F64, {b, b}), tRt = make_view(Rt, F64, {b, b});
-      const int pr[2] = {1, 0};
-      permute(c, tR, pr, tRt);                                           // B = R^T Q_B^T
-    }
-    tsvd_exact(c, Rt, b, b, kk, tau, UB, S);
-    gemm(c, F64, m, kk, b, 1.0, Y, b, 0, UB, kk, 0, 0.0, U, kk);        // U = Q U_B
+    orth_sorted(c, Z, n, b, QB);                                         // B^T P = Q_B R
+    gemm(c, F64, b, b, n, 1.0, Z, b, 1, QB, b, 0, 0.0, L, b);           // L = B Q_B
+    tsvd_core(c, L, b, b, kk, tau, UL, S);
+    gemm(c, F64, m, kk, b, 1.0, Y, b, 0, UL, kk, 0, 0.0, U, kk);        // U = Q U_L
     sign_fix(c, U, m, kk);
     c.arena.release(mk);
     return;
   }
-  if (m >= 4 * n && n >= 32) {
-    const size_t mk = c.arena.mark();
-    double* Q = (double*)c.arena.alloc(sizeof(double) * (size_t)m * n);
-    double* R = (double*)c.arena.alloc(sizeof(double) * (size_t)n * n);
-    double* UR = (double*)c.arena.alloc(sizeof(double) * (size_t)n * kk);
-    double* G = (double*)c.arena.alloc(sizeof(double) * (size_t)n * 32);
-    if (!c.dry)
-      c.check(hipMemcpyAsync(Q, M, sizeof(double) * (size_t)m * n, hipMemcpyDeviceToDevice,
-                             c.stream));
-    orthonormalize(c, Q, m, n, nullptr, G);
-    gemm(c, F64, n, n, m, 1.0, Q, n, 1, M, n, 0, 0.0, R, n);            // R = Q^T M
-    tsvd_exact(c, R, n, n, kk, tau, UR, S);
-    gemm(c, F64, m, kk, n, 1.0, Q, n, 0, UR, kk, 0, 0.0, U, kk);        // U = Q U_R
-    sign_fix(c, U, m, kk);
-    c.arena.release(mk);
-    return;
-  }
-  tsvd_exact(c, M, m, n, k, tau, U, S);
+  if (m >= n)
+    tsvd_core(c, M, m, n, k, tau, U, S);
+  else
+    tsvd_wide(c, M, m, n, k, tau, U, S);
 }
-
-namespace {
-
-void tsvd_exact(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, double* S) {
-  const int kk = std::min(k, std::min(m, n));
-  if (kk <= 0) return;
-  // U comes from the accumulated rotations (orthonormal by construction)
-  // unless M is strictly tall, where it is the normalised columns of M V
-  const bool tall = m > n;
-  const int r = tall ? m : n;       // rows of X
-  const int cc = tall ? n : m;      // columns of X
-  int nb = (cc + JW - 1) / JW;
-  if (nb < 2) nb = 2;
-  if (nb & 1) ++nb;
-  const int cp = nb * JW;
-  const size_t mk = c.arena.mark();
-  double* X = (double*)c.arena.alloc((size_t)r * cp * sizeof(double));
-  double* V = tall ? nullptr : (double*)c.arena.alloc((size_t)cc * cp * sizeof(double));
-  double* sig = (double*)c.arena.alloc((size_t)cp * sizeof(double));
-  int* order = (int*)c.arena.alloc((size_t)kk * sizeof(int));
-  int* flags = (int*)c.arena.alloc(4 * sizeof(int));
-  double* fro = (double*)c.arena.alloc(sizeof(double));
-  norm2(c, M, (int64_t)m * n, fro);
-  double* Ut = (double*)c.arena.alloc((size_t)m * kk * sizeof(double));
-  double* G = (double*)c.arena.alloc((size_t)kk * kk * sizeof(double));
-  if (!c.dry) {
-    int64_t blocks = ((int64_t)r * cp + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(jac_prep_kernel, dim3((unsigned)blocks), dim3(256), 0, c.stream, M, m, n,
-                       tall ? 1 : 0, X, r, cp, V, cc);
-    hipLaunchKernelGGL(jac_flags_init, dim3(1), dim3(1), 0, c.stream, flags);
-    const double eps = 2.220446049250313e-16;
-    const double tol = std::max(std::sqrt((double)r) * eps, 4 * eps);
-    // inner 32 x 32 solve: relative test at n * eps, reachable with the
-    // Rutishauser updates (a stricter test only spins through sweeps)
-    const double tol_in = 32 * eps;
-    const int max_sweeps = 16;
-    for (int sw = 0; sw < max_sweeps; ++sw) {
-      for (int rd = 0; rd < nb - 1; ++rd) {
-        // work of one round if every pair rotates: Gram + update of X (and V)
-        ProfScope ps(c, K_SVD_ROUND,
-                     (double)(nb / 2) * JP * JP * 2.0 * (2.0 * r + (tall ? 0.0 : 2.0 * cc)),
-                     (double)(nb / 2) * JP * 8.0 * (3.0 * r + (tall ? 0.0 : 2.0 * cc)));
-        hipLaunchKernelGGL(jac_round_kernel, dim3(nb / 2), dim3(256), 0, c.stream, X, r,
-                           (int64_t)r, V, tall ? 0 : cc, nb, rd, tol, tol_in, fro, flags);
-      }
-      hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(1), 0, c.stream, flags);
-    }
-    hipLaunchKernelGGL(jac_colnorm_kernel, dim3(cp), dim3(256), 0, c.stream, X, r, cp, sig);
-    hipLaunchKernelGGL(jac_rank_kernel, dim3((cp + 255) / 256), dim3(256), 0, c.stream, sig, cp,
-                       kk, order);
-    hipLaunchKernelGGL(jac_output_kernel, dim3(kk), dim3(256), 0, c.stream, X, r, V, cc, sig,
-                       order, m, kk, tau, Ut, S);
-    c.check_launch();
-  }
-  if (!c.dry)
-    c.check(hipMemcpyAsync(U, Ut, sizeof(double) * (size_t)m * kk, hipMemcpyDeviceToDevice,
-                           c.stream));
-  if (tall) orthonormalize(c, U, m, kk, S, G);   // descending-sigma order
-  c.arena.release(mk);
-}
-
-}  // namespace
 
 void corner_spectrum(Ctx& c, const double* C, int p, int q, int chi, double* out) {
   const int kk = std::min(chi, std::min(p, q));

@@ -86,6 +86,16 @@ def _graded(m, n, decay, seed):
     return U @ np.diag(decay ** np.arange(k)) @ V.T
 
 
+def _zero_cols(m, n, rank, nzero, seed):
+    """Rank-deficient with many exactly zero columns (the shape of the
+    truncated matrices of the reduced move at the cut): exercises the
+    dependent-column handling of the QR preconditioner."""
+    rng = np.random.default_rng(seed)
+    M = rng.standard_normal((m, rank)) @ (rng.standard_normal((rank, n)) * np.exp(-0.2 * np.arange(rank))[:, None])
+    M[:, rng.permutation(n)[:nzero]] = 0.0
+    return M
+
+
 SVD_CASES = [("square16", lambda: np.random.default_rng(0).standard_normal((16, 16)), 8),
              ("tall", lambda: np.random.default_rng(1).standard_normal((300, 40)), 12),
              ("wide", lambda: np.random.default_rng(2).standard_normal((40, 300)), 12),
@@ -93,7 +103,8 @@ SVD_CASES = [("square16", lambda: np.random.default_rng(0).standard_normal((16, 
              ("rankdef", lambda: np.random.default_rng(4).standard_normal((64, 5))
               @ np.random.default_rng(5).standard_normal((5, 70)), 10),
              ("k>rank", lambda: np.random.default_rng(6).standard_normal((24, 24)), 64),
-             ("tall256", lambda: _graded(512, 256, 0.97, 7), 256)]
+             ("tall256", lambda: _graded(512, 256, 0.97, 7), 256),
+             ("zerocols", lambda: _zero_cols(256, 256, 60, 150, 8), 64)]
 
 
 @pytest.mark.parametrize("name,make,k", SVD_CASES)
