@@ -40,6 +40,7 @@
 // of U is sign-fixed: among the rows whose magnitude is within 1e-8
 // (relative) of the largest, the lowest is made positive.
 #include <cmath>
+#include <vector>
 
 #include "ctm_internal.h"
 
@@ -365,74 +366,260 @@ __global__ __launch_bounds__(256) void jac_pick_kernel(const double* __restrict_
   }
 }
 
-// Orthonormalise columns [c0, c0 + nb) of the row-major m x kk matrix U in
-// place, in order, by classical Gram-Schmidt applied twice within the block
-// (earlier blocks are projected out beforehand with GEMMs).  A column whose
-// residual on the first visit is at most 1e-13 of its original norm nrm0, or
-// which on the second visit (final = 1) loses more than half of its unit
-// length again, is numerically dependent on the earlier ones: it is set to
-// zero (and marked in dead[] on the first visit).
-__global__ __launch_bounds__(256) void cgs2_block_kernel(double* __restrict__ U, int m, int kk,
-                                                         int c0, int nb,
-                                                         const double* __restrict__ nrm0,
-                                                         int* __restrict__ dead, int final) {
-  __shared__ double red[32][257];
+// Gram-Schmidt fallback of the in-block step, as a tree (TSQR): the block's
+// rows are cut into chunks of 128; each workgroup orthonormalises its chunk in
+// LDS (classical Gram-Schmidt twice, then a third projection that checks the
+// normalised column: if it loses more than half its length, the column was
+// rounding noise and is dependent), keeping the projection coefficients as
+// the chunk's R factor.  The stacked R factors are reduced the same way until
+// one chunk is left; the Q factors are then multiplied back down the tree.
+// Zero columns of a Q factor come with zero rows of its R factor, so the
+// product stays orthonormal on the nonzero columns.  At the top of the tree
+// dependence follows the block rules: on the first visit a residual at most
+// 1e-13 of the column's original norm nrm0 (recorded in dead[]), on the second
+// a unit column that keeps at most half its length after the re-projection.
+constexpr int TQ = 128;   // rows per chunk
+
+__device__ __forceinline__ double block_sum256(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ __launch_bounds__(256) void tsqr_local_kernel(
+    const double* __restrict__ src, int rows, int64_t lds, int nb, double* __restrict__ q,
+    int64_t ldq, int qcols, double* __restrict__ r, int top, const double* __restrict__ nrm0,
+    int c0, int* __restrict__ dead, int final, const int* __restrict__ healthy) {
+  __shared__ double T[TQ][33];
+  __shared__ double Rl[32][33];
+  __shared__ double red[8][33];
   __shared__ double coef[32];
+  __shared__ double sh[4];
+  __shared__ int dep;
+  if (*healthy) return;   // the Cholesky path took this block
   const int t = threadIdx.x;
+  const int i0 = blockIdx.x * TQ;
+  for (int e = t; e < TQ * 32; e += 256) {
+    const int rr = e >> 5, cc = e & 31;
+    T[rr][cc] = (i0 + rr < rows && cc < nb) ? src[(int64_t)(i0 + rr) * lds + cc] : 0.0;
+  }
+  for (int e = t; e < 32 * 33; e += 256) Rl[e / 33][e % 33] = 0.0;
+  __syncthreads();
+  const int ca = t & 31, cg = t >> 5;   // coefficient a, row group of 16
+  auto colsq = [&](int j) {
+    const double v = (t < TQ) ? T[t][j] : 0.0;
+    return block_sum256(v * v, sh);
+  };
+  // x <- x - sum_{a<j} coef_a q_a, coefficients accumulated into Rl[a][j] * w
+  auto project = [&](int j, double w) {
+    double pp = 0.0;
+    if (ca < j)
+      for (int rr = cg * 16; rr < cg * 16 + 16; ++rr) pp += T[rr][ca] * T[rr][j];
+    red[cg][ca] = pp;
+    __syncthreads();
+    if (t < j) {
+      double cs = 0.0;
+      for (int g = 0; g < 8; ++g) cs += red[g][t];
+      coef[t] = cs;
+      Rl[t][j] += w * cs;
+    }
+    __syncthreads();
+    if (t < TQ) {
+      double x = T[t][j];
+      for (int aa = 0; aa < j; ++aa) x -= coef[aa] * T[t][aa];
+      T[t][j] = x;
+    }
+    __syncthreads();
+  };
   for (int j = 0; j < nb; ++j) {
-    const int cj = c0 + j;
-    if (final && dead[cj]) {
-      for (int i = t; i < m; i += 256) U[(int64_t)i * kk + cj] = 0.0;
+    if (top && final && dead[c0 + j]) {
+      if (t < TQ) T[t][j] = 0.0;
       __syncthreads();
       continue;
     }
-    for (int pass = 0; pass < 2; ++pass) {
-      if (j > 0) {
-        double part[32];
-        for (int a = 0; a < j; ++a) part[a] = 0.0;
-        for (int i = t; i < m; i += 256) {
-          const double x = U[(int64_t)i * kk + cj];
-          for (int a = 0; a < j; ++a) part[a] += U[(int64_t)i * kk + c0 + a] * x;
-        }
-        for (int a = 0; a < j; ++a) red[a][t] = part[a];
-        __syncthreads();
-        if (t < j) {
-          double sacc = 0.0;
-          for (int q = 0; q < 256; ++q) sacc += red[t][q];
-          coef[t] = sacc;
-        }
-        __syncthreads();
-        for (int i = t; i < m; i += 256) {
-          double x = U[(int64_t)i * kk + cj];
-          for (int a = 0; a < j; ++a) x -= coef[a] * U[(int64_t)i * kk + c0 + a];
-          U[(int64_t)i * kk + cj] = x;
-        }
-        __syncthreads();
+    const double x0 = sqrt(colsq(j));
+    project(j, 1.0);
+    project(j, 1.0);
+    const double r1 = sqrt(colsq(j));
+    if (t == 0) {
+      bool d;
+      if (top) d = final ? !(r1 > 0.5) : !(r1 > 1e-13 * nrm0[c0 + j]);
+      else d = !(r1 > 1e-13 * x0);
+      dep = d ? 1 : 0;
+    }
+    __syncthreads();
+    double rjj = 0.0;
+    if (!dep) {
+      if (t < TQ) T[t][j] /= r1;
+      __syncthreads();
+      project(j, r1);
+      const double r2 = sqrt(colsq(j));
+      if (t == 0) dep = (r2 > 0.5) ? 0 : 1;
+      __syncthreads();
+      if (!dep) {
+        if (t < TQ) T[t][j] /= r2;
+        rjj = r1 * r2;
       }
     }
-    double sq = 0.0;
-    for (int i = t; i < m; i += 256) {
-      const double x = U[(int64_t)i * kk + cj];
-      sq += x * x;
-    }
-    red[0][t] = sq;
-    __syncthreads();
+    if (dep && t < TQ) T[t][j] = 0.0;
     if (t == 0) {
-      double sacc = 0.0;
-      for (int q = 0; q < 256; ++q) sacc += red[0][q];
-      const double nr = sqrt(sacc);
-      // first visit: residual at rounding level of the original column;
-      // second visit (unit norm on entry): more than half the length lost
-      // to the earlier columns means the first visit normalised rounding
-      // noise, so the column is dependent to working precision
-      const bool dep = final ? !(nr > 0.5) : !(nr > 1e-13 * nrm0[cj]);
-      if (!final) dead[cj] = dep ? 1 : 0;
-      coef[0] = dep ? 0.0 : 1.0 / nr;
+      Rl[j][j] = rjj;
+      if (top && !final) dead[c0 + j] = dep;
     }
     __syncthreads();
-    const double inv = coef[0];
-    for (int i = t; i < m; i += 256) U[(int64_t)i * kk + cj] *= inv;
+  }
+  for (int e = t; e < TQ * 32; e += 256) {
+    const int rr = e >> 5, cc = e & 31;
+    if (i0 + rr < rows && cc < qcols) q[(int64_t)(i0 + rr) * ldq + cc] = T[rr][cc];
+  }
+  if (r != nullptr)
+    for (int e = t; e < 32 * 32; e += 256) {
+      const int rr = e >> 5, cc = e & 31;
+      r[((int64_t)blockIdx.x * 32 + rr) * 32 + cc] = Rl[rr][cc];
+    }
+}
+
+// dst rows of chunk b = Q rows of chunk b (TQ x 32, ld 32) times W rows
+// [32 b, 32 b + 32) (ld 32); nb columns.
+__global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restrict__ Q, int rows,
+                                                         const double* __restrict__ W, int nb,
+                                                         double* __restrict__ dst, int64_t ldd,
+                                                         const int* __restrict__ healthy) {
+  __shared__ double Ws[32][33];
+  __shared__ double Qs[TQ][33];
+  if (*healthy) return;
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * TQ;
+  for (int e = t; e < 32 * 32; e += 256) Ws[e >> 5][e & 31] = W[((int64_t)blockIdx.x * 32 + (e >> 5)) * 32 + (e & 31)];
+  for (int e = t; e < TQ * 32; e += 256) {
+    const int rr = e >> 5, cc = e & 31;
+    Qs[rr][cc] = (i0 + rr < rows) ? Q[(int64_t)(i0 + rr) * 32 + cc] : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < TQ * 32; e += 256) {
+    const int rr = e >> 5, cc = e & 31;
+    if (i0 + rr >= rows || cc >= nb) continue;
+    double v = 0.0;
+    for (int a2 = 0; a2 < 32; ++a2) v += Qs[rr][a2] * Ws[a2][cc];
+    dst[(int64_t)(i0 + rr) * ldd + cc] = v;
+  }
+}
+
+// Cholesky path of the in-block step.  G (nb x nb) is the Gram matrix of the
+// block's columns after the projection of the earlier blocks.  One wavefront
+// factors G = R^T R and inverts R.  The block is "healthy" when the
+// condition number of the column-scaled block, estimated from R^{-1}, is at
+// most 1e6 on the first visit (Cholesky QR then leaves orthogonality errors
+// below ~1e-4, which the second visit removes) and at most twice its value
+// for an orthonormal block (the number of nonzero columns) on the second,
+// every nonzero column keeps a pivot d_j >= delta G_jj (delta = 1e-12, then
+// 0.25: unit columns that lose more than half their length are left to the
+// Gram-Schmidt fallback, which decides dependence), and on the first visit
+// no column is at or below 1e-13 of its original norm.  Exactly zero columns
+// are dead.  Ri = R^{-1} (dead rows and columns zero).
+__global__ __launch_bounds__(64) void chol_block_kernel(const double* __restrict__ G, int nb,
+                                                        int c0, const double* __restrict__ nrm0,
+                                                        int* __restrict__ dead, int final,
+                                                        double* __restrict__ Ri,
+                                                        int* __restrict__ healthy) {
+  __shared__ double R[32][33];
+  __shared__ double Gs[32][33];
+  __shared__ int ok, isdead[32];
+  const int l = threadIdx.x;
+  for (int e = l; e < nb * nb; e += 64) Gs[e / nb][e % nb] = G[e];
+  for (int e = l; e < 32 * 33; e += 64) R[e / 33][e % 33] = 0.0;
+  if (l == 0) ok = 1;
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    // lane j: pivot
+    if (l == j) {
+      double d = Gs[j][j];
+      for (int a = 0; a < j; ++a) d -= R[a][j] * R[a][j];
+      const double gjj = Gs[j][j];
+      int dd = 0;
+      if (gjj == 0.0) {
+        dd = 1;                       // exactly zero column
+      } else {
+        const double delta = final ? 0.25 : 1e-12;
+        if (!(d >= delta * gjj)) ok = 0;
+        if (!final && !(sqrt(gjj) > 1e-13 * nrm0[c0 + j])) ok = 0;
+      }
+      isdead[j] = dd;
+      R[j][j] = (dd || !(d > 0.0)) ? 0.0 : sqrt(d);
+    }
     __syncthreads();
+    if (l > j && l < nb) {
+      double v = Gs[j][l];
+      for (int a = 0; a < j; ++a) v -= R[a][j] * R[a][l];
+      R[j][l] = (R[j][j] > 0.0) ? v / R[j][j] : 0.0;
+    }
+    __syncthreads();
+  }
+  // column l of R^{-1} by back substitution, and its share of
+  // ||diag(sqrt(G_jj)) R^{-1}||_F^2
+  double col[32];
+  double part = 0.0;
+  int live = 0;
+  if (l < nb) {
+    for (int r = 0; r < 32; ++r) col[r] = 0.0;
+    if (R[l][l] > 0.0) {
+      col[l] = 1.0 / R[l][l];
+      for (int r = l - 1; r >= 0; --r) {
+        if (!(R[r][r] > 0.0)) continue;
+        double v = 0.0;
+        for (int a = r + 1; a <= l; ++a) v += R[r][a] * col[a];
+        col[r] = -v / R[r][r];
+      }
+    }
+    for (int r = 0; r < nb; ++r) {
+      const double x = sqrt(Gs[r][r]) * col[r];
+      part += x * x;
+    }
+    live = isdead[l] ? 0 : 1;
+  }
+  // the columns of R diag(1/sqrt(G_jj)) have unit norm, so
+  // kappa_F = sqrt(live columns) * ||diag(sqrt(G_jj)) R^{-1}||_F bounds the
+  // condition number of the column-scaled block, which sets the accuracy of
+  // Cholesky QR (orthogonality ~ eps kappa^2)
+  for (int off = 32; off > 0; off >>= 1) {
+    part += __shfl_xor(part, off);
+    live += __shfl_xor(live, off);
+  }
+  const double kappa = sqrt((double)live * part);
+  // an orthonormal block has kappa_F = live exactly
+  const int good = ok && (kappa <= (final ? 2.0 * (double)(live > 0 ? live : 1) : 1e6));
+  if (l < nb) {
+    for (int r = 0; r < nb; ++r) Ri[r * nb + l] = col[r];
+    if (!final && good) dead[c0 + l] = isdead[l];
+  }
+  if (l == 0) *healthy = good;
+}
+
+// U[:, c0 : c0 + nb] <- U[:, c0 : c0 + nb] Ri (row-major, ld kk), when the
+// block is healthy.  Each workgroup takes 64 rows.
+__global__ __launch_bounds__(256) void apply_ri_kernel(double* __restrict__ U, int m, int kk,
+                                                       int c0, int nb,
+                                                       const double* __restrict__ Ri,
+                                                       const int* __restrict__ healthy) {
+  __shared__ double Rs[32][33];
+  __shared__ double P[64][33];
+  if (!*healthy) return;
+  const int t = threadIdx.x;
+  const int i0 = blockIdx.x * 64;
+  for (int e = t; e < nb * nb; e += 256) Rs[e / nb][e % nb] = Ri[e];
+  for (int e = t; e < 64 * nb; e += 256) {
+    const int r = e / nb, cc = e % nb;
+    P[r][cc] = (i0 + r < m) ? U[(int64_t)(i0 + r) * kk + c0 + cc] : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < 64 * nb; e += 256) {
+    const int r = e / nb, cc = e % nb;
+    if (i0 + r >= m) continue;
+    double v = 0.0;
+    for (int a = 0; a <= cc; ++a) v += P[r][a] * Rs[a][cc];
+    U[(int64_t)(i0 + r) * kk + c0 + cc] = v;
   }
 }
 
@@ -499,10 +686,58 @@ __global__ void spec_finish_kernel(const double* __restrict__ S, int kk, int chi
 
 namespace {
 
+// The Gram-Schmidt tree for block [c0, c0 + nbk) of A (kernels exit at once
+// when the Cholesky path has taken the block).
+void tsqr_fallback(Ctx& c, double* A, int m, int kk, int c0, int nbk, const double* nrm0,
+                   int* dead, int pass, const int* healthy) {
+  const size_t mk = c.arena.mark();
+  const double* src = A + c0;
+  int64_t lds = kk;
+  int rows = m;
+  std::vector<double*> qs;
+  std::vector<int> rws;
+  for (;;) {
+    const int chunks = (rows + TQ - 1) / TQ;
+    const bool top = chunks == 1;
+    double* q = top && qs.empty() ? A + c0 : (double*)c.arena.alloc(sizeof(double) * (size_t)rows * 32);
+    const int64_t ldq = top && qs.empty() ? kk : 32;
+    double* r = top ? nullptr : (double*)c.arena.alloc(sizeof(double) * (size_t)chunks * 32 * 32);
+    if (!c.dry) {
+      ProfScope ps(c, K_SVD_OTHER, 6.0 * rows * nbk * nbk, 8.0 * 2.0 * rows * nbk);
+      // scratch Q factors carry all 32 columns (zeros beyond nbk)
+      const int qcols = (q == A + c0) ? nbk : 32;
+      hipLaunchKernelGGL(tsqr_local_kernel, dim3(chunks), dim3(256), 0, c.stream, src, rows, lds,
+                         nbk, q, ldq, qcols, r, top ? 1 : 0, nrm0, c0, dead, pass, healthy);
+      c.check_launch();
+    }
+    qs.push_back(q);
+    rws.push_back(rows);
+    if (top) break;
+    src = r;
+    lds = 32;
+    rows = chunks * 32;
+  }
+  // multiply back down: W_l = Q_l W_{l+1}; the last product lands in A
+  const double* W = qs.back();
+  for (int l = (int)qs.size() - 2; l >= 0; --l) {
+    double* out = (l == 0) ? A + c0 : (double*)c.arena.alloc(sizeof(double) * (size_t)rws[l] * 32);
+    const int64_t ldo = (l == 0) ? kk : 32;
+    if (!c.dry) {
+      ProfScope ps(c, K_SVD_OTHER, 2.0 * rws[l] * 32.0 * nbk, 8.0 * 3.0 * rws[l] * 32);
+      hipLaunchKernelGGL(tsqr_apply_kernel, dim3((rws[l] + TQ - 1) / TQ), dim3(256), 0, c.stream,
+                         qs[l], rws[l], W, (l == 0) ? nbk : 32, out, ldo, healthy);
+      c.check_launch();
+    }
+    W = out;
+  }
+  c.arena.release(mk);
+}
+
 // Orthonormalise the kk columns of row-major A (m x kk) in place, in order,
 // by block classical Gram-Schmidt applied twice (BCGS2): for each block of 32
 // columns, project out the earlier blocks (one GEMM pair), orthonormalise
-// inside the block (classical Gram-Schmidt twice), and repeat both steps.
+// inside the block (Cholesky QR when the block is well conditioned, else
+// classical Gram-Schmidt twice), and repeat both steps.
 // The second projection comes after the first in-block normalisation, so a
 // nearly dependent column, which shrinks to a small residual inside the
 // block, is still made orthogonal to the earlier blocks.  Columns dependent
@@ -517,6 +752,9 @@ void orthonormalize(Ctx& c, double* A, int m, int kk) {
   double* nrm0 = (double*)c.arena.alloc(sizeof(double) * (size_t)kk);
   int* dead = (int*)c.arena.alloc(sizeof(int) * (size_t)kk);
   double* G = (double*)c.arena.alloc(sizeof(double) * (size_t)kk * OB);
+  double* Gb = (double*)c.arena.alloc(sizeof(double) * OB * OB);
+  double* Ri = (double*)c.arena.alloc(sizeof(double) * OB * OB);
+  int* healthy = (int*)c.arena.alloc(sizeof(int));
   if (!c.dry) {
     ProfScope ps(c, K_SVD_OTHER, 0.0, 8.0 * (double)m * kk);
     hipLaunchKernelGGL(rm_colsq_kernel, dim3((kk + 255) / 256, chunks), dim3(256), 0, c.stream, A,
@@ -532,12 +770,18 @@ void orthonormalize(Ctx& c, double* A, int m, int kk) {
         gemm(c, F64, c0, nbk, m, 1.0, A, kk, 1, A + c0, kk, 0, 0.0, G, nbk);
         gemm(c, F64, m, nbk, c0, -1.0, A, kk, 0, G, nbk, 0, 1.0, A + c0, kk);
       }
+      // in-block: Cholesky QR of the block when it is well conditioned,
+      // classical Gram-Schmidt twice otherwise (decided on the device)
+      gemm(c, F64, nbk, nbk, m, 1.0, A + c0, kk, 1, A + c0, kk, 0, 0.0, Gb, nbk);
       if (!c.dry) {
-        ProfScope ps(c, K_SVD_OTHER, 4.0 * m * nbk * nbk, 8.0 * 6.0 * m * nbk);
-        hipLaunchKernelGGL(cgs2_block_kernel, dim3(1), dim3(256), 0, c.stream, A, m, kk, c0, nbk,
-                           nrm0, dead, pass);
+        ProfScope ps(c, K_SVD_OTHER, 2.0 * m * nbk * nbk, 8.0 * 2.0 * m * nbk);
+        hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(64), 0, c.stream, Gb, nbk, c0, nrm0,
+                           dead, pass, Ri, healthy);
+        hipLaunchKernelGGL(apply_ri_kernel, dim3((m + 63) / 64), dim3(256), 0, c.stream, A, m, kk,
+                           c0, nbk, Ri, healthy);
         c.check_launch();
       }
+      tsqr_fallback(c, A, m, kk, c0, nbk, nrm0, dead, pass, healthy);
     }
   }
   c.arena.release(mk);
