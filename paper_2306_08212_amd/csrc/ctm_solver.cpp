@@ -10,8 +10,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <stdexcept>
+#include <vector>
 
 #include "../../include/ctm.h"
 #include "ctm_internal.h"
@@ -37,6 +39,19 @@ struct ctm_solver {
   double* h4 = nullptr;      // device d^4 operator
   size_t persist = 0;
   Profiler prof;
+  // independent truncations of one insertion run concurrently on these
+  // streams (default priority), forked from and joined to ctx.stream
+  static constexpr int kAux = 4, kMaxBranch = 8;
+  hipStream_t aux[kAux] = {};
+  hipEvent_t ev_fork = nullptr;
+  hipEvent_t ev_join[kMaxBranch] = {};
+  ~ctm_solver() {
+    for (hipStream_t& st : aux)
+      if (st) (void)hipStreamDestroy(st);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    for (hipEvent_t& e : ev_join)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -78,9 +93,61 @@ Tensor reshape(const Tensor& t, std::initializer_list<int64_t> dims) {
   return o;
 }
 
-// Truncated isometry of a row-major m x n F64 matrix: U (m x kk) at dst.
-Tensor isometry(ctm_solver* s, const Tensor& M, int64_t m, int64_t n, void* dst) {
+// Runs independent pieces of work concurrently.  Each branch gets its own
+// slice of the workspace (sized by a dry run of the branch), its own stream
+// and its own range of random-generator calls, so its kernels and results do
+// not depend on the other branches or on their timing.  Branches write their
+// results into buffers the caller allocated before the fork.
+void run_branches(ctm_solver* s, const std::vector<std::function<void(Ctx&)>>& fs) {
   Ctx& c = s->ctx;
+  const int n = (int)fs.size();
+  if (n > ctm_solver::kMaxBranch) throw std::runtime_error("too many branches");
+  std::vector<size_t> need(n);
+  for (int b = 0; b < n; ++b) {
+    Ctx d;
+    d.dry = true;
+    d.arena.dry = true;
+    fs[b](d);
+    need[b] = d.arena.peak + 256;
+  }
+  // the slices are released on return: every later use of that memory is
+  // ordered after the join on ctx.stream
+  const size_t mk = c.arena.mark();
+  std::vector<char*> base(n);
+  for (int b = 0; b < n; ++b) base[b] = (char*)c.arena.alloc(need[b]);
+  if (c.dry && std::getenv("CTM_DEBUG_MEM"))
+    for (int b = 0; b < n; ++b)
+      std::fprintf(stderr, "  branch %d/%d needs %.1f MB (top %.1f MB)\n", b, n, need[b] / 1e6,
+                   c.arena.top / 1e6);
+  const uint64_t r0 = c.rng_calls;
+  c.rng_calls = r0 + 64 * (uint64_t)(n + 1);
+  if (c.dry || c.arena.overflow) {
+    c.arena.release(mk);
+    return;
+  }
+  const bool par = s->ev_fork != nullptr;
+  if (par) c.check(hipEventRecord(s->ev_fork, c.stream));
+  for (int b = 0; b < n; ++b) {
+    Ctx k;
+    k.stream = par ? s->aux[b % ctm_solver::kAux] : c.stream;
+    k.prof = c.prof;
+    k.dev_flags = c.dev_flags;
+    k.arena.base = base[b];
+    k.arena.cap = need[b];
+    k.rng_calls = r0 + 64 * (uint64_t)(b + 1);
+    if (par) c.check(hipStreamWaitEvent(k.stream, s->ev_fork, 0));
+    fs[b](k);
+    c.check(k.hip_err);
+    if (k.arena.overflow) c.arena.overflow = true;
+    if (par) c.check(hipEventRecord(s->ev_join[b], k.stream));
+  }
+  if (par)
+    for (int b = 0; b < n; ++b) c.check(hipStreamWaitEvent(c.stream, s->ev_join[b], 0));
+  c.arena.release(mk);
+}
+
+// Truncated isometry of a row-major m x n F64 matrix: U (m x kk) at dst.
+Tensor isometry(ctm_solver* s, Ctx& c, const Tensor& M, int64_t m, int64_t n, void* dst) {
   const int kk = (int)std::min<int64_t>(s->chi, std::min(m, n));
   const size_t mk = c.arena.mark();
   double* S = (double*)c.arena.alloc(sizeof(double) * std::max(kk, 1));
@@ -89,50 +156,47 @@ Tensor isometry(ctm_solver* s, const Tensor& M, int64_t m, int64_t n, void* dst)
   return make_view(dst, F64, {m, kk});
 }
 
-Tensor double_layer(ctm_solver* s, const Tensor& S) {
-  Tensor a = contract(s->ctx, S, "slurd", S, "sLURD", "lLuUrRdD", F64, F64);
-  return a;
+Tensor double_layer(Ctx& c, const Tensor& S) {
+  return contract(c, S, "slurd", S, "sLURD", "lLuUrRdD", F64, F64);
 }
 
 // ---------------------------------------------------------------- anchors
 
 // Standard 4-index isometry v_z[j, kd, bd, nu] (Sec. II, Fig. 2(c)).
-Tensor anchor_standard(ctm_solver* s, int r, int z, void* dst) {
-  Ctx& c = s->ctx;
+Tensor anchor_standard(ctm_solver* s, Ctx& c, int r, int z, void* dst) {
   const int w = 1 - z;
   const int64_t D = s->D;
   Tensor C1 = env_view(s, kC, 1, z, r), T1 = env_view(s, kT, 1, z, r), T2 = env_view(s, kT, 2, z, r);
   Tensor T2w = env_view(s, kT, 2, w, r), C2w = env_view(s, kC, 2, w, r), T3w = env_view(s, kT, 3, w, r);
   const int64_t nj = T1.dims[0], nq = T2.dims[3], nj2 = T3w.dims[3];
   const size_t mk = c.arena.mark();
-  Tensor az = double_layer(s, site_view(s, r, z));
+  Tensor az = double_layer(c, site_view(s, r, z));
   Tensor X = contract(c, C1, "mn", T2, "nuvq", "muvq", F64, F64);
   Tensor Y = contract(c, T1, "jklm", X, "muvq", "jkluvq", F64, F64);
   Tensor Q1 = contract(c, Y, "jkluvq", az, "kluvrRdD", "jdDqrR", F64, F64);
-  Tensor aw = double_layer(s, site_view(s, r, w));
+  Tensor aw = double_layer(c, site_view(s, r, w));
   Tensor X2 = contract(c, T2w, "quvn", C2w, "nm", "quvm", F64, F64);
   Tensor Y2 = contract(c, X2, "quvm", T3w, "mrRj", "quvrRj", F64, F64);
   Tensor Q2 = contract(c, Y2, "quvrRj", aw, "lLuvrRdD", "qlLdDj", F64, F64);
   const int64_t m = nj * D * D, k = nq * D * D, n = D * D * nj2;
   Tensor M = c.alloc(F64, {m, n});
   gemm(c, F64, (int)m, (int)n, (int)k, 1.0, Q1.p, k, 0, Q2.p, n, 0, 0.0, M.p, n);
-  Tensor U = isometry(s, M, m, n, dst);
+  Tensor U = isometry(s, c, M, m, n, dst);
   c.arena.release(mk);
   return make_view(dst, F64, {nj, D, D, U.dims[1]});
 }
 
 // Two-stage isometry of X[i,k,b,j] (bonded on (i,k,b)): v1 [i,k,mu], v2
 // [mu,b,nu], X''[nu,j] (Appendix, Fig. A(c)).  Outputs at the given buffers.
-void split_iso(ctm_solver* s, const Tensor& X, void* d1, void* d2, void* dxx, Tensor* v1o,
-               Tensor* v2o, Tensor* xxo) {
-  Ctx& c = s->ctx;
+void split_iso(ctm_solver* s, Ctx& c, const Tensor& X, void* d1, void* d2, void* dxx,
+               Tensor* v1o, Tensor* v2o, Tensor* xxo) {
   const int64_t ni = X.dims[0], D = X.dims[1], nj = X.dims[3];
   const size_t mk = c.arena.mark();
-  Tensor v1 = isometry(s, X, ni * D, D * nj, d1);
+  Tensor v1 = isometry(s, c, X, ni * D, D * nj, d1);
   const int64_t c1 = v1.dims[1];
   v1 = reshape(v1, {ni, D, c1});
   Tensor Xp = contract(c, v1, "ikm", X, "iklj", "mlj", F64, F64);
-  Tensor v2 = isometry(s, Xp, c1 * D, nj, d2);
+  Tensor v2 = isometry(s, c, Xp, c1 * D, nj, d2);
   const int64_t c2 = v2.dims[1];
   v2 = reshape(v2, {c1, D, c2});
   Tensor Xpp = contract(c, v2, "mln", Xp, "mlj", "nj", F64, F64);
@@ -146,9 +210,8 @@ void split_iso(ctm_solver* s, const Tensor& X, void* d1, void* d2, void* dxx, Te
 // Fig. 4(b)): T[p,k,b,q], site S[s, in, p-side, open, q-side] in the compute
 // type; the p-side bond takes (vp1, vp2), the q-side bond (vq1, vq2).
 // Returns out[nu_p, ko, bo, nu_q] in F64.
-Tensor chain(ctm_solver* s, const Tensor& T, const Tensor& S, const Tensor& vp1,
+Tensor chain(ctm_solver* s, Ctx& c, const Tensor& T, const Tensor& S, const Tensor& vp1,
              const Tensor& vp2, const Tensor& vq1, const Tensor& vq2) {
-  Ctx& c = s->ctx;
   const int cp = cdt(s);
   Tensor X1 = contract(c, T, "pkbq", vp1, "pim", "kbqim", cp, cp);
   Tensor X2 = contract(c, X1, "kbqim", S, "skioj", "bqmsoj", cp, cp);
@@ -162,52 +225,49 @@ struct SplitV {
   Tensor v1, v2;
 };
 
-// Split isometries (v^1_z[j,kd,mu], v^2_z[mu,bd,nu]) from the reduced
-// half-network [C1 T2 C2; T1 z T3] (Secs. III-IV, Figs. 3-4, Appendix).
-SplitV anchor_reduced(ctm_solver* s, int r, int z, void* d1, void* d2) {
-  Ctx& c = s->ctx;
-  const int64_t D = s->D, cap = s->cap, chi = s->chi;
-  Tensor C1 = env_view(s, kC, 1, z, r), T1 = env_view(s, kT, 1, z, r), T2 = env_view(s, kT, 2, z, r);
-  Tensor C2 = env_view(s, kC, 2, z, r), T3 = env_view(s, kT, 3, z, r);
+// Helper isometries and compressed corner of one side of the reduced
+// half-network [C1 T2 C2; T1 z T3] (Appendix, Fig. A(c)): side 0 splits
+// {C1, T1}, side 1 splits {C2, T3}.
+struct SideIso {
+  Tensor v1, v2, cc;
+  void *b1 = nullptr, *b2 = nullptr, *bc = nullptr;
+};
+
+void side_iso(ctm_solver* s, Ctx& c, int r, int z, int side, SideIso* o) {
+  const size_t mk = c.arena.mark();
+  Tensor X;
+  if (side == 0) {
+    Tensor C1 = env_view(s, kC, 1, z, r), T1 = env_view(s, kT, 1, z, r);
+    X = contract(c, C1, "mi", T1, "jklm", "iklj", F64, F64);
+  } else {
+    Tensor C2 = env_view(s, kC, 2, z, r), T3 = env_view(s, kT, 3, z, r);
+    X = contract(c, C2, "im", T3, "mklj", "iklj", F64, F64);
+  }
+  split_iso(s, c, X, o->b1, o->b2, o->bc, &o->v1, &o->v2, &o->cc);
+  c.arena.release(mk);
+}
+
+// Split isometries (v^1_z[j,kd,mu], v^2_z[mu,bd,nu]) of the reduced move
+// (Secs. III-IV, Figs. 3-4): T'2 from the sequential ket-then-bra absorption
+// of z into T2 between the two sides' helper isometries, M' = C'1 T'2 C'2,
+// v^1 from M' as (chi D) x (D chi), v^2 from N = v^1^T M' as (chi' D) x chi.
+SplitV anchor_reduced(ctm_solver* s, Ctx& c, int r, int z, const SideIso& L, const SideIso& R,
+                      void* d1, void* d2) {
+  const int64_t D = s->D;
+  Tensor T2 = env_view(s, kT, 2, z, r), T1 = env_view(s, kT, 1, z, r);
+  Tensor T3 = env_view(s, kT, 3, z, r);
   const int64_t nj = T1.dims[0], nj2 = T3.dims[3];
   const size_t mk = c.arena.mark();
-  // buffers for the helper isometries and the compressed corners
-  void* bl1 = c.arena.alloc(sizeof(double) * cap * D * chi);
-  void* bl2 = c.arena.alloc(sizeof(double) * chi * D * chi);
-  void* br1 = c.arena.alloc(sizeof(double) * cap * D * chi);
-  void* br2 = c.arena.alloc(sizeof(double) * chi * D * chi);
-  void* bc1 = c.arena.alloc(sizeof(double) * chi * cap);
-  void* bc2 = c.arena.alloc(sizeof(double) * chi * cap);
-  void* btp = c.arena.alloc(sizeof(double) * chi * D * D * chi);
-  Tensor vl1, vl2, Cp1, vr1, vr2, Cp2;
-  {
-    const size_t m2 = c.arena.mark();
-    Tensor L = contract(c, C1, "mi", T1, "jklm", "iklj", F64, F64);
-    split_iso(s, L, bl1, bl2, bc1, &vl1, &vl2, &Cp1);
-    c.arena.release(m2);
-  }
-  {
-    const size_t m2 = c.arena.mark();
-    Tensor R = contract(c, C2, "im", T3, "mklj", "iklj", F64, F64);
-    split_iso(s, R, br1, br2, bc2, &vr1, &vr2, &Cp2);
-    c.arena.release(m2);
-  }
-  Tensor Tp2;
-  {
-    const size_t m2 = c.arena.mark();
-    const int cp = cdt(s);
-    Tensor S = make_view(s->sT2[r][z], cp, {s->d, D, D, D, D});
-    Tensor t = chain(s, T2, S, vl1, vl2, vr1, vr2);
-    Tp2 = keep(c, t, btp);
-    c.arena.release(m2);
-  }
-  Tensor Mp = contract(c, Cp1, "nj", Tp2, "ndDo", "jdDo", F64, F64);
-  Mp = contract(c, Mp, "jdDo", Cp2, "ok", "jdDk", F64, F64);
-  Tensor v1 = isometry(s, Mp, nj * D, D * nj2, d1);
+  const int cp = cdt(s);
+  Tensor S = make_view(s->sT2[r][z], cp, {s->d, D, D, D, D});
+  Tensor Tp2 = chain(s, c, T2, S, L.v1, L.v2, R.v1, R.v2);
+  Tensor Mp = contract(c, L.cc, "nj", Tp2, "ndDo", "jdDo", F64, F64);
+  Mp = contract(c, Mp, "jdDo", R.cc, "ok", "jdDk", F64, F64);
+  Tensor v1 = isometry(s, c, Mp, nj * D, D * nj2, d1);
   const int64_t c1 = v1.dims[1];
   v1 = reshape(v1, {nj, D, c1});
   Tensor N = contract(c, v1, "jdm", Mp, "jdDk", "mDk", F64, F64);
-  Tensor v2 = isometry(s, N, c1 * D, nj2, d2);
+  Tensor v2 = isometry(s, c, N, c1 * D, nj2, d2);
   const int64_t c2 = v2.dims[1];
   v2 = reshape(v2, {c1, D, c2});
   c.arena.release(mk);
@@ -240,76 +300,116 @@ void store_env(ctm_solver* s, int e, const Tensor& t) {
 }
 
 // Insert one column into the left environment (frame r) and truncate.
+// Independent work runs as concurrent branches: the two anchors (standard
+// move) or the four side isometries and then the two split anchors (reduced
+// move), and finally the updates of the two rows x = a, b.
 void insert_column(ctm_solver* s, int r) {
   Ctx& c = s->ctx;
   const int64_t D = s->D, cap = s->cap, chi = s->chi;
   const bool stdm = insertion_standard(s, r);
+  // the standard move's (chi D^2) x (D^2 chi) objects dominate the
+  // workspace; when they are large its branches run one after the other
+  const bool big_standard = (double)cap * D * D * cap * D * D * 8.0 > 1e9;
   const size_t mk = c.arena.mark();
   // anchors
   Tensor V4[2];
   SplitV VS[2];
-  for (int z = 0; z < 2; ++z) {
-    if (stdm) {
-      void* dv = c.arena.alloc(sizeof(double) * cap * D * D * chi);
-      V4[z] = anchor_standard(s, r, z, dv);
+  if (stdm) {
+    void* dv[2];
+    for (int z = 0; z < 2; ++z) dv[z] = c.arena.alloc(sizeof(double) * cap * D * D * chi);
+    auto a0 = [&](Ctx& k) { V4[0] = anchor_standard(s, k, r, 0, dv[0]); };
+    auto a1 = [&](Ctx& k) { V4[1] = anchor_standard(s, k, r, 1, dv[1]); };
+    if (big_standard) {
+      run_branches(s, {a0});
+      run_branches(s, {a1});
     } else {
-      void* d1 = c.arena.alloc(sizeof(double) * cap * D * chi);
-      void* d2 = c.arena.alloc(sizeof(double) * chi * D * chi);
-      VS[z] = anchor_reduced(s, r, z, d1, d2);
+      run_branches(s, {a0, a1});
     }
+  } else {
+    SideIso side[2][2];   // [z][side]
+    for (int z = 0; z < 2; ++z)
+      for (int sd = 0; sd < 2; ++sd) {
+        side[z][sd].b1 = c.arena.alloc(sizeof(double) * cap * D * chi);
+        side[z][sd].b2 = c.arena.alloc(sizeof(double) * chi * D * chi);
+        side[z][sd].bc = c.arena.alloc(sizeof(double) * chi * cap);
+      }
+    std::vector<std::function<void(Ctx&)>> fs;
+    for (int z = 0; z < 2; ++z)
+      for (int sd = 0; sd < 2; ++sd)
+        fs.push_back([&, z, sd](Ctx& k) { side_iso(s, k, r, z, sd, &side[z][sd]); });
+    run_branches(s, fs);
+    void* d1[2];
+    void* d2[2];
+    for (int z = 0; z < 2; ++z) {
+      d1[z] = c.arena.alloc(sizeof(double) * cap * D * chi);
+      d2[z] = c.arena.alloc(sizeof(double) * chi * D * chi);
+    }
+    run_branches(s, {[&](Ctx& k) { VS[0] = anchor_reduced(s, k, r, 0, side[0][0], side[0][1], d1[0], d2[0]); },
+                     [&](Ctx& k) { VS[1] = anchor_reduced(s, k, r, 1, side[1][0], side[1][1], d1[1], d2[1]); }});
   }
   // new tensors, staged until all six are done
   Tensor nC1[2], nT1[2], nC4[2];
+  void *bC1[2], *bT1[2], *bC4[2];
+  for (int y = 0; y < 2; ++y) {
+    bC1[y] = c.arena.alloc(sizeof(double) * cap * cap);
+    bT1[y] = c.arena.alloc(sizeof(double) * cap * D * D * cap);
+    bC4[y] = c.arena.alloc(sizeof(double) * cap * cap);
+  }
   const int cp = cdt(s);
-  for (int x = 0; x < 2; ++x) {
+  auto update_row = [&](Ctx& k, int x) {
     const int y = 1 - x;
     Tensor C1x = env_view(s, kC, 1, x, r), T2x = env_view(s, kT, 2, x, r);
     Tensor T1x = env_view(s, kT, 1, x, r);
     Tensor C4x = env_view(s, kC, 4, x, r), T4x = env_view(s, kT, 4, x, r);
-    void* bC1 = c.arena.alloc(sizeof(double) * cap * cap);
-    void* bT1 = c.arena.alloc(sizeof(double) * cap * D * D * cap);
-    void* bC4 = c.arena.alloc(sizeof(double) * cap * cap);
     {
-      const size_t m2 = c.arena.mark();
-      Tensor G = contract(c, C1x, "jm", T2x, "mubq", "jubq", F64, F64);
+      const size_t m2 = k.arena.mark();
+      Tensor G = contract(k, C1x, "jm", T2x, "mubq", "jubq", F64, F64);
       Tensor t;
       if (stdm) {
-        t = contract(c, G, "jubq", V4[y], "jubn", "nq", F64, F64);
+        t = contract(k, G, "jubq", V4[y], "jubn", "nq", F64, F64);
       } else {
-        Tensor G1 = contract(c, G, "jubq", VS[y].v1, "jum", "mbq", F64, F64);
-        t = contract(c, G1, "mbq", VS[y].v2, "mbn", "nq", F64, F64);
+        Tensor G1 = contract(k, G, "jubq", VS[y].v1, "jum", "mbq", F64, F64);
+        t = contract(k, G1, "mbq", VS[y].v2, "mbn", "nq", F64, F64);
       }
-      nC1[y] = keep(c, t, bC1);
-      c.arena.release(m2);
+      nC1[y] = keep(k, t, bC1[y]);
+      k.arena.release(m2);
     }
     {
-      const size_t m2 = c.arena.mark();
+      const size_t m2 = k.arena.mark();
       Tensor t;
       if (stdm) {
-        Tensor a = double_layer(s, site_view(s, r, x));
-        Tensor Z = contract(c, T1x, "pklq", V4[y], "quvn", "pkluvn", F64, F64);
-        Z = contract(c, Z, "pkluvn", a, "kluvrRdD", "pnrRdD", F64, F64);
-        t = contract(c, Z, "pnrRdD", V4[x], "pdDm", "mrRn", F64, F64);
+        Tensor a = double_layer(k, site_view(s, r, x));
+        Tensor Z = contract(k, T1x, "pklq", V4[y], "quvn", "pkluvn", F64, F64);
+        Z = contract(k, Z, "pkluvn", a, "kluvrRdD", "pnrRdD", F64, F64);
+        t = contract(k, Z, "pnrRdD", V4[x], "pdDm", "mrRn", F64, F64);
       } else {
         Tensor S = make_view(s->sT1[r][x], cp, {s->d, D, D, D, D});
-        t = chain(s, T1x, S, VS[x].v1, VS[x].v2, VS[y].v1, VS[y].v2);
+        t = chain(s, k, T1x, S, VS[x].v1, VS[x].v2, VS[y].v1, VS[y].v2);
       }
-      nT1[y] = keep(c, t, bT1);
-      c.arena.release(m2);
+      nT1[y] = keep(k, t, bT1[y]);
+      k.arena.release(m2);
     }
     {
-      const size_t m2 = c.arena.mark();
-      Tensor G4 = contract(c, C4x, "mj", T4x, "pkbm", "jkbp", F64, F64);
+      const size_t m2 = k.arena.mark();
+      Tensor G4 = contract(k, C4x, "mj", T4x, "pkbm", "jkbp", F64, F64);
       Tensor t;
       if (stdm) {
-        t = contract(c, G4, "jkbp", V4[x], "jkbn", "pn", F64, F64);
+        t = contract(k, G4, "jkbp", V4[x], "jkbn", "pn", F64, F64);
       } else {
-        Tensor G5 = contract(c, G4, "jkbp", VS[x].v1, "jkm", "mbp", F64, F64);
-        t = contract(c, G5, "mbp", VS[x].v2, "mbn", "pn", F64, F64);
+        Tensor G5 = contract(k, G4, "jkbp", VS[x].v1, "jkm", "mbp", F64, F64);
+        t = contract(k, G5, "mbp", VS[x].v2, "mbn", "pn", F64, F64);
       }
-      nC4[y] = keep(c, t, bC4);
-      c.arena.release(m2);
+      nC4[y] = keep(k, t, bC4[y]);
+      k.arena.release(m2);
     }
+  };
+  auto u0 = [&](Ctx& k) { update_row(k, 0); };
+  auto u1 = [&](Ctx& k) { update_row(k, 1); };
+  if (stdm && big_standard) {
+    run_branches(s, {u0});
+    run_branches(s, {u1});
+  } else {
+    run_branches(s, {u0, u1});
   }
   for (int y = 0; y < 2; ++y) {
     store_env(s, env_index(kC, stored_i(1, r), y), nC1[y]);
@@ -568,6 +668,9 @@ int ctm_init(const ctm_config* cfg, const double* A, const double* B, int ptrs_o
     fill_from_cfg(s, cfg);
     s->ctx.arena.base = (char*)cfg->workspace;
     s->ctx.arena.cap = cfg->workspace_bytes;
+    for (hipStream_t& st : s->aux) s->ctx.check(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    s->ctx.check(hipEventCreateWithFlags(&s->ev_fork, hipEventDisableTiming));
+    for (hipEvent_t& e : s->ev_join) s->ctx.check(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     setup(s, A, B, ptrs_on_device);
     s->ctx.check(hipStreamSynchronize(s->ctx.stream));
     int st = status_from(s);
