@@ -22,11 +22,14 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------- FP64
 
-constexpr int F64_BM = 64, F64_BN = 64, F64_BK = 16;
+constexpr int F64_BM = 64, F64_BN = 64, F64_BK = 32;
+constexpr int F64_PER = F64_BM * F64_BK / 256;   // elements of each operand per thread
 
 // Split-K: blockIdx.z takes K range [z * kchunk, min(K, (z + 1) * kchunk)).
 // With part != nullptr the raw partial products go to part (one M x N slab
 // per (z, batch) pair) and a separate pass sums them in a fixed order.
+// The next K tile is fetched into registers while the current one is
+// multiplied from LDS.
 __global__ __launch_bounds__(256) void gemm_f64_kernel(
     int M, int N, int K, double alpha, const double* __restrict__ A, int64_t lda, int ta,
     const double* __restrict__ B, int64_t ldb, int tb, double beta, double* __restrict__ C,
@@ -48,24 +51,38 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  for (int k0 = kbeg; k0 < kend; k0 += F64_BK) {
-    for (int e = tid; e < F64_BM * F64_BK; e += 256) {
+  double ra[F64_PER], rb[F64_PER];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < F64_PER; ++q) {
+      const int e = tid + 256 * q;
       int mm, kk;
       if (!ta) { mm = e / F64_BK; kk = e % F64_BK; } else { kk = e / F64_BM; mm = e % F64_BM; }
       const int gm = m0 + mm, gk = k0 + kk;
-      double v = 0.0;
-      if (gm < M && gk < kend) v = ta ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-      As[kk][mm] = v;
+      ra[q] = (gm < M && gk < kend) ? (ta ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk]) : 0.0;
+      int nn, kb;
+      if (!tb) { kb = e / F64_BN; nn = e % F64_BN; } else { nn = e / F64_BK; kb = e % F64_BK; }
+      const int gn = n0 + nn, gkb = k0 + kb;
+      rb[q] = (gn < N && gkb < kend) ? (tb ? B[(int64_t)gn * ldb + gkb] : B[(int64_t)gkb * ldb + gn]) : 0.0;
     }
-    for (int e = tid; e < F64_BN * F64_BK; e += 256) {
-      int nn, kk;
-      if (!tb) { kk = e / F64_BN; nn = e % F64_BN; } else { nn = e / F64_BK; kk = e % F64_BK; }
-      const int gn = n0 + nn, gk = k0 + kk;
-      double v = 0.0;
-      if (gn < N && gk < kend) v = tb ? B[(int64_t)gn * ldb + gk] : B[(int64_t)gk * ldb + gn];
-      Bs[kk][nn] = v;
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < F64_PER; ++q) {
+      const int e = tid + 256 * q;
+      int mm, kk;
+      if (!ta) { mm = e / F64_BK; kk = e % F64_BK; } else { kk = e / F64_BM; mm = e % F64_BM; }
+      As[kk][mm] = ra[q];
+      int nn, kb;
+      if (!tb) { kb = e / F64_BN; nn = e % F64_BN; } else { nn = e / F64_BK; kb = e % F64_BK; }
+      Bs[kb][nn] = rb[q];
     }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += F64_BK) {
+    stash();
     __syncthreads();
+    if (k0 + F64_BK < kend) fetch(k0 + F64_BK);
 #pragma unroll
     for (int kk = 0; kk < F64_BK; kk += 4) {
       const int kr = kk + (lane >> 4);

@@ -28,8 +28,8 @@
 // cannot reach and the sweeps never end.
 //
 // Columns are grouped in blocks of 16; one workgroup takes a pair of blocks
-// (32 columns), forms their 32 x 32 Gram matrix, diagonalises it with at most
-// two cyclic Jacobi sweeps in LDS (the outer sweeps finish the job), and
+// (32 columns), forms their 32 x 32 Gram matrix, applies one cyclic Jacobi
+// sweep to it in LDS (the outer sweeps finish the job), and
 // applies the resulting rotation to the 32 columns of X and of J.  Block
 // pairs follow a round-robin tournament, so the pairs of one round are
 // disjoint and run as one launch.  A device flag ends the sweeps once a full
@@ -101,7 +101,8 @@ __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double 
         piv[t][1] = aqq + tt * apq;
       }
       __syncthreads();
-      // rows: G <- J^T G (pivot 2x2 blocks are set exactly below)
+      // rows: G <- J^T G, and the pivot 2x2 blocks set exactly (no update
+      // of either phase touches them)
       for (int task = t; task < (JP / 2) * JP; task += blockDim.x) {
         const int i = task / JP, k = task % JP;
         const int p = pq[2 * i], q = pq[2 * i + 1];
@@ -111,6 +112,13 @@ __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double 
           G[p][k] = c * gp - s * gq;
           G[q][k] = s * gp + c * gq;
         }
+      }
+      if (t < JP / 2 && cs[2 * t + 1] != 0.0) {
+        const int p = pq[2 * t], q = pq[2 * t + 1];
+        G[p][p] = piv[t][0];
+        G[q][q] = piv[t][1];
+        G[p][q] = 0.0;
+        G[q][p] = 0.0;
       }
       __syncthreads();
       // columns: G <- G J, J <- J J
@@ -128,14 +136,6 @@ __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double 
           J[k][p] = c * jp - s * jq;
           J[k][q] = s * jp + c * jq;
         }
-      }
-      __syncthreads();
-      if (t < JP / 2 && cs[2 * t + 1] != 0.0) {
-        const int p = pq[2 * t], q = pq[2 * t + 1];
-        G[p][p] = piv[t][0];
-        G[q][q] = piv[t][1];
-        G[p][q] = 0.0;
-        G[q][p] = 0.0;
       }
       __syncthreads();
     }
@@ -169,16 +169,32 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
   const int t = threadIdx.x;
   auto col = [&](int a) { return a < JW ? bi * JW + a : bj * JW + (a - JW); };
 
-  // Gram of the 32 columns
+  // Gram of the 32 columns; chunks of 32 rows go through LDS, the next one
+  // is fetched into registers while the current one is used
   const int ga = t >> 3, gb = (t & 7) * 4;
   double g0 = 0, g1 = 0, g2 = 0, g3 = 0;
-  for (int row0 = 0; row0 < r; row0 += 32) {
-    for (int e = t; e < 32 * JP; e += 256) {
+  double pre[4];
+  auto fetch = [&](const double* src, int rows, int64_t ld, int row0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q;
       const int a = e >> 5, rr = e & 31;
       const int gr = row0 + rr;
-      chunk[rr][a] = gr < r ? X[(int64_t)col(a) * ldx + gr] : 0.0;
+      pre[q] = gr < rows ? src[(int64_t)col(a) * ld + gr] : 0.0;
     }
+  };
+  auto stash = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = t + 256 * q;
+      chunk[e & 31][e >> 5] = pre[q];
+    }
+  };
+  fetch(X, r, ldx, 0);
+  for (int row0 = 0; row0 < r; row0 += 32) {
+    stash();
     __syncthreads();
+    if (row0 + 32 < r) fetch(X, r, ldx, row0 + 32);
 #pragma unroll 8
     for (int rr = 0; rr < 32; ++rr) {
       const double x = chunk[rr][ga];
@@ -209,13 +225,11 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
 
   // X[:, cols] <- X[:, cols] J   (thread: column b = t/8, 4 consecutive rows)
   const int ob = t >> 3, orr = (t & 7) * 4;
+  fetch(X, r, ldx, 0);
   for (int row0 = 0; row0 < r; row0 += 32) {
-    for (int e = t; e < 32 * JP; e += 256) {
-      const int a = e >> 5, rr = e & 31;
-      const int gr = row0 + rr;
-      chunk[rr][a] = gr < r ? X[(int64_t)col(a) * ldx + gr] : 0.0;
-    }
+    stash();
     __syncthreads();
+    if (row0 + 32 < r) fetch(X, r, ldx, row0 + 32);
     double o[4] = {0, 0, 0, 0};
     for (int a = 0; a < JP; ++a) {
       const double j = J[a][ob];
@@ -228,13 +242,11 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
     __syncthreads();
   }
   if (V != nullptr) {
+    fetch(V, vr, vr, 0);
     for (int row0 = 0; row0 < vr; row0 += 32) {
-      for (int e = t; e < 32 * JP; e += 256) {
-        const int a = e >> 5, rr = e & 31;
-        const int gr = row0 + rr;
-        chunk[rr][a] = gr < vr ? V[(int64_t)col(a) * vr + gr] : 0.0;
-      }
+      stash();
       __syncthreads();
+      if (row0 + 32 < vr) fetch(V, vr, vr, row0 + 32);
       double o[4] = {0, 0, 0, 0};
       for (int a = 0; a < JP; ++a) {
         const double j = J[a][ob];
@@ -519,25 +531,31 @@ __global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restric
 // Gram-Schmidt fallback, which decides dependence), and on the first visit
 // no column is at or below 1e-13 of its original norm.  Exactly zero columns
 // are dead.  Ri = R^{-1} (dead rows and columns zero).
-__global__ __launch_bounds__(64) void chol_block_kernel(const double* __restrict__ G, int nb,
-                                                        int c0, const double* __restrict__ nrm0,
-                                                        int* __restrict__ dead, int final,
-                                                        double* __restrict__ Ri,
-                                                        int* __restrict__ healthy) {
+__global__ __launch_bounds__(256) void chol_block_kernel(const double* __restrict__ G, int nb,
+                                                         int c0, const double* __restrict__ nrm0,
+                                                         int* __restrict__ dead, int final,
+                                                         double* __restrict__ Ri,
+                                                         int* __restrict__ healthy) {
+  __shared__ double W[32][33];    // G, overwritten by the trailing updates
   __shared__ double R[32][33];
-  __shared__ double Gs[32][33];
+  __shared__ double X[32][33];    // R^{-1}
+  __shared__ double gd[32];       // diagonal of G
   __shared__ int ok, isdead[32];
-  const int l = threadIdx.x;
-  for (int e = l; e < nb * nb; e += 64) Gs[e / nb][e % nb] = G[e];
-  for (int e = l; e < 32 * 33; e += 64) R[e / 33][e % 33] = 0.0;
-  if (l == 0) ok = 1;
+  const int t = threadIdx.x;
+  for (int e = t; e < 32 * 32; e += 256) {
+    const int i = e >> 5, j = e & 31;
+    W[i][j] = (i < nb && j < nb) ? G[i * nb + j] : 0.0;
+    R[i][j] = 0.0;
+    X[i][j] = (i == j && i < nb) ? 1.0 : 0.0;
+  }
+  if (t < nb) gd[t] = G[t * nb + t];
+  if (t == 0) ok = 1;
   __syncthreads();
+  // right-looking Cholesky: the pivot of step j is W[j][j] after the
+  // updates of steps < j; the trailing block is then updated in parallel
   for (int j = 0; j < nb; ++j) {
-    // lane j: pivot
-    if (l == j) {
-      double d = Gs[j][j];
-      for (int a = 0; a < j; ++a) d -= R[a][j] * R[a][j];
-      const double gjj = Gs[j][j];
+    if (t == 0) {
+      const double d = W[j][j], gjj = gd[j];
       int dd = 0;
       if (gjj == 0.0) {
         dd = 1;                       // exactly zero column
@@ -550,51 +568,56 @@ __global__ __launch_bounds__(64) void chol_block_kernel(const double* __restrict
       R[j][j] = (dd || !(d > 0.0)) ? 0.0 : sqrt(d);
     }
     __syncthreads();
-    if (l > j && l < nb) {
-      double v = Gs[j][l];
-      for (int a = 0; a < j; ++a) v -= R[a][j] * R[a][l];
-      R[j][l] = (R[j][j] > 0.0) ? v / R[j][j] : 0.0;
+    const double rjj = R[j][j];
+    if (t > j && t < nb) R[j][t] = rjj > 0.0 ? W[j][t] / rjj : 0.0;
+    __syncthreads();
+    const int w = nb - j - 1;
+    for (int e = t; e < w * w; e += 256) {
+      const int i = j + 1 + e / w, k = j + 1 + e % w;
+      W[i][k] -= R[j][i] * R[j][k];
     }
     __syncthreads();
   }
-  // column l of R^{-1} by back substitution, and its share of
-  // ||diag(sqrt(G_jj)) R^{-1}||_F^2
-  double col[32];
-  double part = 0.0;
-  int live = 0;
-  if (l < nb) {
-    for (int r = 0; r < 32; ++r) col[r] = 0.0;
-    if (R[l][l] > 0.0) {
-      col[l] = 1.0 / R[l][l];
-      for (int r = l - 1; r >= 0; --r) {
-        if (!(R[r][r] > 0.0)) continue;
-        double v = 0.0;
-        for (int a = r + 1; a <= l; ++a) v += R[r][a] * col[a];
-        col[r] = -v / R[r][r];
-      }
+  // R^{-1} by backward elimination on X = I, one row of R at a time from the
+  // bottom (dead rows and columns stay zero)
+  for (int r = nb - 1; r >= 0; --r) {
+    const double rr = R[r][r];
+    if (t >= r && t < nb) X[r][t] = rr > 0.0 ? X[r][t] / rr : 0.0;
+    __syncthreads();
+    const int w = nb - r;
+    for (int e = t; e < r * w; e += 256) {
+      const int i = e / w, k = r + e % w;
+      X[i][k] -= R[i][r] * X[r][k];
     }
-    for (int r = 0; r < nb; ++r) {
-      const double x = sqrt(Gs[r][r]) * col[r];
-      part += x * x;
-    }
-    live = isdead[l] ? 0 : 1;
+    __syncthreads();
   }
-  // the columns of R diag(1/sqrt(G_jj)) have unit norm, so
   // kappa_F = sqrt(live columns) * ||diag(sqrt(G_jj)) R^{-1}||_F bounds the
-  // condition number of the column-scaled block, which sets the accuracy of
-  // Cholesky QR (orthogonality ~ eps kappa^2)
-  for (int off = 32; off > 0; off >>= 1) {
-    part += __shfl_xor(part, off);
-    live += __shfl_xor(live, off);
+  // condition number of the column-scaled block (the columns of
+  // R diag(1/sqrt(G_jj)) have unit norm), which sets the accuracy of
+  // Cholesky QR (orthogonality ~ eps kappa^2).  Wave 0 holds the columns.
+  if (t < 64) {
+    double part = 0.0;
+    int live = 0;
+    if (t < nb) {
+      for (int r = 0; r <= t; ++r) {
+        const double x = sqrt(gd[r]) * X[r][t];
+        part += x * x;
+      }
+      live = isdead[t] ? 0 : 1;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      part += __shfl_xor(part, off);
+      live += __shfl_xor(live, off);
+    }
+    const double kappa = sqrt((double)live * part);
+    // an orthonormal block has kappa_F = live exactly
+    const int good = ok && (kappa <= (final ? 2.0 * (double)(live > 0 ? live : 1) : 1e6));
+    if (t < nb) {
+      for (int r = 0; r < nb; ++r) Ri[r * nb + t] = X[r][t];
+      if (!final && good) dead[c0 + t] = isdead[t];
+    }
+    if (t == 0) *healthy = good;
   }
-  const double kappa = sqrt((double)live * part);
-  // an orthonormal block has kappa_F = live exactly
-  const int good = ok && (kappa <= (final ? 2.0 * (double)(live > 0 ? live : 1) : 1e6));
-  if (l < nb) {
-    for (int r = 0; r < nb; ++r) Ri[r * nb + l] = col[r];
-    if (!final && good) dead[c0 + l] = isdead[l];
-  }
-  if (l == 0) *healthy = good;
 }
 
 // U[:, c0 : c0 + nb] <- U[:, c0 : c0 + nb] Ri (row-major, ld kk), when the
@@ -775,7 +798,7 @@ void orthonormalize(Ctx& c, double* A, int m, int kk) {
       gemm(c, F64, nbk, nbk, m, 1.0, A + c0, kk, 1, A + c0, kk, 0, 0.0, Gb, nbk);
       if (!c.dry) {
         ProfScope ps(c, K_SVD_OTHER, 2.0 * m * nbk * nbk, 8.0 * 2.0 * m * nbk);
-        hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(64), 0, c.stream, Gb, nbk, c0, nrm0,
+        hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(256), 0, c.stream, Gb, nbk, c0, nrm0,
                            dead, pass, Ri, healthy);
         hipLaunchKernelGGL(apply_ri_kernel, dim3((m + 63) / 64), dim3(256), 0, c.stream, A, m, kk,
                            c0, nbk, Ri, healthy);
@@ -857,7 +880,7 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
     // inner test strictly below the outer one, so a block the inner solve
     // leaves converged also passes the outer test
     const double tol_in = std::min(32.0, 0.5 * std::max((double)r, 4.0)) * eps;
-    const int inner_sweeps = 2;
+    const int inner_sweeps = 1;
     const int max_sweeps = 14;
     for (int sw = 0; sw < max_sweeps; ++sw) {
       for (int rd = 0; rd < nb - 1; ++rd) {
