@@ -78,6 +78,7 @@ struct Ctx {
   bool dry = false;
   hipError_t hip_err = hipSuccess;
   int* dev_flags = nullptr;   // [0] numeric error, [1..] scratch counters
+  double* work = nullptr;     // device tallies of data-dependent work (profiling)
   uint64_t rng_calls = 0;     // counter of randomised truncations (seeds)
   void check(hipError_t e) {
     if (e != hipSuccess && hip_err == hipSuccess) hip_err = e;

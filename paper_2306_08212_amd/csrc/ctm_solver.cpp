@@ -132,6 +132,7 @@ void run_branches(ctm_solver* s, const std::vector<std::function<void(Ctx&)>>& f
     k.stream = par ? s->aux[b % ctm_solver::kAux] : c.stream;
     k.prof = c.prof;
     k.dev_flags = c.dev_flags;
+    k.work = c.work;
     k.arena.base = base[b];
     k.arena.cap = need[b];
     k.rng_calls = r0 + 64 * (uint64_t)(b + 1);
@@ -550,6 +551,7 @@ void setup(ctm_solver* s, const double* A, const double* B, int on_device) {
   s->scal = (double*)c.arena.alloc(64 * sizeof(double));
   s->h4 = (double*)c.arena.alloc(d * d * d * d * sizeof(double));
   c.dev_flags = (int*)c.arena.alloc(16 * sizeof(int));
+  c.work = (double*)c.arena.alloc(8 * sizeof(double));
   s->persist = c.arena.mark();
   if (c.arena.overflow) return;
   if (!c.dry) {
@@ -867,6 +869,10 @@ int ctm_profile(ctm_solver* s, int enable) {
   s->ctx.check(hipStreamSynchronize(s->ctx.stream));
   s->prof.clear();
   s->ctx.prof = enable ? &s->prof : nullptr;
+  if (enable) {
+    fill(s->ctx, s->ctx.work, F64, 8, 0.0);
+    s->ctx.check(hipStreamSynchronize(s->ctx.stream));
+  }
   return status_from(s);
 }
 
@@ -875,10 +881,17 @@ int ctm_profile_read(ctm_solver* s, int cls, long long* launches, double* ms, do
   if (!s || cls < 0 || cls >= K_NCLASS) return CTM_EINVAL;
   s->ctx.check(hipStreamSynchronize(s->ctx.stream));
   s->prof.collect();
+  double f = s->prof.flops[cls], b = s->prof.bytes[cls];
+  if (cls == K_SVD_ROUND) {   // data-dependent work, tallied on the device
+    double w[2] = {0.0, 0.0};
+    s->ctx.check(hipMemcpy(w, s->ctx.work, sizeof(w), hipMemcpyDeviceToHost));
+    f = w[0];
+    b = w[1];
+  }
   if (launches) *launches = s->prof.n[cls];
   if (ms) *ms = s->prof.ms[cls];
-  if (flops) *flops = s->prof.flops[cls];
-  if (bytes) *bytes = s->prof.bytes[cls];
+  if (flops) *flops = f;
+  if (bytes) *bytes = b;
   return status_from(s);
 }
 

@@ -331,28 +331,36 @@ void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A, i
   // k == 0 needs no special case: the K loop is empty and C = beta * C.
   const double es = dtype == F64 ? 8.0 : (dtype == F32 ? 4.0 : 2.0);
   const double eo = dtype == F64 ? 8.0 : 4.0;
-  ProfScope ps(c, dtype == F64 ? K_GEMM_F64 : (dtype == F32 ? K_GEMM_F32 : K_GEMM_BF16),
-               2.0 * m * n * (double)k * batch,
-               ((double)m * k + (double)k * n) * es * batch + (double)m * n * eo * batch);
   if (dtype == F64) {
     const int tm = (m + F64_BM - 1) / F64_BM, tn = (n + F64_BN - 1) / F64_BN;
     dim3 grid(tm * tn, batch, splits);
-    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, c.stream, m, n, k, alpha,
-                       (const double*)A, lda, ta, (const double*)B, ldb, tb, beta, (double*)C,
-                       ldc, sA, sB, sC, tn, kchunk, part);
+    {
+      ProfScope ps(c, K_GEMM_F64, 2.0 * m * n * (double)k * batch,
+                   ((double)m * k + (double)k * n) * es * batch +
+                       (double)m * n * eo * batch * splits);
+      hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, c.stream, m, n, k, alpha,
+                         (const double*)A, lda, ta, (const double*)B, ldb, tb, beta, (double*)C,
+                         ldc, sA, sB, sC, tn, kchunk, part);
+    }
     if (splits > 1) {
+      ProfScope ps(c, K_REDUCE, (double)m * n * batch * splits,
+                   (double)m * n * batch * 8.0 * (splits + 1));
       int64_t blocks = ((int64_t)m * n * batch + 255) / 256;
       if (blocks > 4096) blocks = 4096;
       hipLaunchKernelGGL(gemm_f64_splitk_sum, dim3((unsigned)blocks), dim3(256), 0, c.stream, m, n,
                          batch, splits, alpha, part, beta, (double*)C, ldc, sC);
     }
   } else if (dtype == F32) {
+    ProfScope ps(c, K_GEMM_F32, 2.0 * m * n * (double)k * batch,
+                 ((double)m * k + (double)k * n) * es * batch + (double)m * n * eo * batch);
     const int tm = (m + F32_BM - 1) / F32_BM, tn = (n + F32_BN - 1) / F32_BN;
     dim3 grid(tm * tn, batch);
     hipLaunchKernelGGL(gemm_f32_kernel, grid, dim3(256), 0, c.stream, m, n, k, (float)alpha,
                        (const float*)A, lda, ta, (const float*)B, ldb, tb, (float)beta,
                        (float*)C, ldc, sA, sB, sC, tn);
   } else {
+    ProfScope ps(c, K_GEMM_BF16, 2.0 * m * n * (double)k * batch,
+                 ((double)m * k + (double)k * n) * es * batch + (double)m * n * eo * batch);
     const int tm = (m + B16_BM - 1) / B16_BM, tn = (n + B16_BN - 1) / B16_BN;
     dim3 grid(tm * tn, batch);
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, c.stream, m, n, k, (float)alpha,

@@ -151,7 +151,8 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
                                                         int round, double tol, double tol_in,
                                                         int inner_sweeps,
                                                         const double* __restrict__ fro,
-                                                        int* __restrict__ flags) {
+                                                        int* __restrict__ flags,
+                                                        double* __restrict__ work) {
   __shared__ double G[JP][JP + 1];
   __shared__ double J[JP][JP + 1];
   __shared__ double chunk[32][JP + 1];
@@ -219,6 +220,14 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
     }
   }
   __syncthreads();
+  // algorithmic work of this block pair, for the profiler: the Gram
+  // (2 r 32^2 flop, r 32 doubles read) and, when it rotates, X J and V J
+  // (2 (r + vr) 32^2 flop, (r + vr) 32 doubles read and written)
+  if (work != nullptr && t == 0) {
+    const double rot = any ? 1.0 : 0.0;
+    atomicAdd(&work[0], 2.0 * JP * JP * (r + rot * (r + vr)));
+    atomicAdd(&work[1], 8.0 * JP * (r + rot * 2.0 * (r + vr)));
+  }
   if (!any) return;
   lds_sym_jacobi(G, J, tol_in, gnoise, thr, inner_sweeps, &sflag, cs, pq);
   if (t == 0) atomicAdd(&flags[1], 1);
@@ -885,10 +894,11 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
     for (int sw = 0; sw < max_sweeps; ++sw) {
       for (int rd = 0; rd < nb - 1; ++rd) {
         // work of one round if every pair rotates: Gram + update of X and V
-        ProfScope ps(c, K_SVD_ROUND, (double)(nb / 2) * JP * JP * 2.0 * (2.0 * r + 2.0 * n),
-                     (double)(nb / 2) * JP * 8.0 * (3.0 * r + 2.0 * n));
+        // the work is data dependent: the kernel tallies it on the device
+        ProfScope ps(c, K_SVD_ROUND, 0.0, 0.0);
         hipLaunchKernelGGL(jac_round_kernel, dim3(nb / 2), dim3(256), 0, c.stream, X, r,
-                           (int64_t)r, V, n, nb, rd, tol, tol_in, inner_sweeps, fro, flags);
+                           (int64_t)r, V, n, nb, rd, tol, tol_in, inner_sweeps, fro, flags,
+                           c.prof ? c.work : nullptr);
       }
       hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(1), 0, c.stream, flags);
     }

@@ -8,6 +8,9 @@
 // count and a fixed summation order, so results are bitwise reproducible.
 #include <cmath>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "ctm_internal.h"
 
 namespace ctm {
@@ -279,6 +282,13 @@ void Profiler::clear() {
 }
 
 void permute(Ctx& c, const Tensor& in, const int* perm, Tensor& out, double scale) {
+  if (std::getenv("CTM_DEBUG_PERM") && in.numel() >= (1 << 20)) {
+    std::fprintf(stderr, "permute dt %d->%d dims", in.dt, out.dt);
+    for (int i = 0; i < in.nd; ++i) std::fprintf(stderr, " %lld", (long long)in.dims[i]);
+    std::fprintf(stderr, " perm");
+    for (int i = 0; i < in.nd; ++i) std::fprintf(stderr, " %d", perm[i]);
+    std::fprintf(stderr, "\n");
+  }
   if (c.dry || in.numel() == 0) return;
   ProfScope ps(c, K_PERMUTE, 0.0,
                (double)in.numel() * (double)(dtype_size(in.dt) + dtype_size(out.dt)));
