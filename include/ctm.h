@@ -127,6 +127,7 @@ int ctm_set_env(ctm_solver *s, int e, const double *host_in, int p, int q);
 /* Moves done so far. */
 int ctm_moves_done(const ctm_solver *s);
 
+
 /* Switch the precision of the absorption chains (enum ctm_precision) for the
  * moves that follow; the environment is kept. */
 int ctm_set_precision(ctm_solver *s, int precision);

@@ -125,6 +125,7 @@ void permute(Ctx& c, const Tensor& in, const int* perm, Tensor& out,
              double scale = 1.0);
 
 void fill(Ctx& c, void* p, int dt, int64_t n, double v);
+void copy_bytes(Ctx& c, void* dst, const void* src, size_t bytes);
 
 // Frobenius norm of x (F64) into *nrm (device); x *= 1/norm afterwards with
 // normalize(); a zero or non-finite norm raises the numeric error flag.

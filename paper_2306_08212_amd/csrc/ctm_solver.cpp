@@ -12,7 +12,9 @@
 #include <cstring>
 #include <functional>
 #include <new>
+#include <exception>
 #include <stdexcept>
+#include <thread>
 #include <vector>
 
 #include "../../include/ctm.h"
@@ -82,7 +84,7 @@ Tensor keep(Ctx& c, const Tensor& t, void* dst) {
   out.p = dst;
   if (!c.dry && t.p != dst && t.bytes() > 0) {
     ProfScope ps(c, K_COPY, 0.0, 2.0 * t.bytes());
-    c.check(hipMemcpyAsync(dst, t.p, t.bytes(), hipMemcpyDeviceToDevice, c.stream));
+    copy_bytes(c, dst, t.p, t.bytes());
   }
   return out;
 }
@@ -127,8 +129,9 @@ void run_branches(ctm_solver* s, const std::vector<std::function<void(Ctx&)>>& f
   }
   const bool par = s->ev_fork != nullptr;
   if (par) c.check(hipEventRecord(s->ev_fork, c.stream));
+  std::vector<Ctx> ks(n);
   for (int b = 0; b < n; ++b) {
-    Ctx k;
+    Ctx& k = ks[b];
     k.stream = par ? s->aux[b % ctm_solver::kAux] : c.stream;
     k.prof = c.prof;
     k.dev_flags = c.dev_flags;
@@ -136,15 +139,45 @@ void run_branches(ctm_solver* s, const std::vector<std::function<void(Ctx&)>>& f
     k.arena.base = base[b];
     k.arena.cap = need[b];
     k.rng_calls = r0 + 64 * (uint64_t)(b + 1);
-    if (par) c.check(hipStreamWaitEvent(k.stream, s->ev_fork, 0));
+  }
+  // each branch is issued from its own host thread (kernel launches cost
+  // host time, and the branches share no host state); with the profiler on
+  // they are issued in order from this thread
+  auto issue = [&](int b) {
+    Ctx& k = ks[b];
+    if (par) k.check(hipStreamWaitEvent(k.stream, s->ev_fork, 0));
     fs[b](k);
-    c.check(k.hip_err);
-    if (k.arena.overflow) c.arena.overflow = true;
-    if (par) c.check(hipEventRecord(s->ev_join[b], k.stream));
+    if (par) k.check(hipEventRecord(s->ev_join[b], k.stream));
+  };
+  std::vector<std::exception_ptr> errs(n);
+  if (par && c.prof == nullptr && n > 1) {
+    std::vector<std::thread> th;
+    for (int b = 1; b < n; ++b)
+      th.emplace_back([&, b] {
+        try {
+          issue(b);
+        } catch (...) {
+          errs[b] = std::current_exception();
+        }
+      });
+    try {
+      issue(0);
+    } catch (...) {
+      errs[0] = std::current_exception();
+    }
+    for (std::thread& t : th) t.join();
+  } else {
+    for (int b = 0; b < n; ++b) issue(b);
+  }
+  for (int b = 0; b < n; ++b) {
+    c.check(ks[b].hip_err);
+    if (ks[b].arena.overflow) c.arena.overflow = true;
   }
   if (par)
     for (int b = 0; b < n; ++b) c.check(hipStreamWaitEvent(c.stream, s->ev_join[b], 0));
   c.arena.release(mk);
+  for (int b = 0; b < n; ++b)
+    if (errs[b]) std::rethrow_exception(errs[b]);
 }
 
 // Truncated isometry of a row-major m x n F64 matrix: U (m x kk) at dst.
@@ -853,6 +886,7 @@ int ctm_set_env(ctm_solver* s, int e, const double* host_in, int p, int q) {
 }
 
 int ctm_moves_done(const ctm_solver* s) { return s ? s->moves : -1; }
+
 
 int ctm_set_precision(ctm_solver* s, int precision) {
   if (!s || precision < CTM_FP64 || precision > CTM_BF16) return CTM_EINVAL;

@@ -40,6 +40,8 @@
 // of U is sign-fixed: among the rows whose magnitude is within 1e-8
 // (relative) of the largest, the lowest is made positive.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "ctm_internal.h"
@@ -232,41 +234,34 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
   lds_sym_jacobi(G, J, tol_in, gnoise, thr, inner_sweeps, &sflag, cs, pq);
   if (t == 0) atomicAdd(&flags[1], 1);
 
-  // X[:, cols] <- X[:, cols] J   (thread: column b = t/8, 4 consecutive rows)
+  // [X; V][:, cols] <- [X; V][:, cols] J, as one stream of 32-row chunks over
+  // the rows of X and then of V (thread: column b = t/8, 4 consecutive rows)
   const int ob = t >> 3, orr = (t & 7) * 4;
-  fetch(X, r, ldx, 0);
-  for (int row0 = 0; row0 < r; row0 += 32) {
+  const int nx = (r + 31) / 32, nv = (V != nullptr) ? (vr + 31) / 32 : 0;
+  auto fetch_chunk = [&](int ci) {
+    if (ci < nx) fetch(X, r, ldx, ci * 32);
+    else fetch(V, vr, vr, (ci - nx) * 32);
+  };
+  fetch_chunk(0);
+  for (int ci = 0; ci < nx + nv; ++ci) {
     stash();
     __syncthreads();
-    if (row0 + 32 < r) fetch(X, r, ldx, row0 + 32);
+    if (ci + 1 < nx + nv) fetch_chunk(ci + 1);
     double o[4] = {0, 0, 0, 0};
     for (int a = 0; a < JP; ++a) {
       const double j = J[a][ob];
       for (int q = 0; q < 4; ++q) o[q] += chunk[orr + q][a] * j;
     }
+    const bool isx = ci < nx;
+    const int row0 = isx ? ci * 32 : (ci - nx) * 32;
+    const int rows = isx ? r : vr;
+    double* dst = isx ? X : V;
+    const int64_t ld = isx ? ldx : (int64_t)vr;
     for (int q = 0; q < 4; ++q) {
       const int gr = row0 + orr + q;
-      if (gr < r) X[(int64_t)col(ob) * ldx + gr] = o[q];
+      if (gr < rows) dst[(int64_t)col(ob) * ld + gr] = o[q];
     }
     __syncthreads();
-  }
-  if (V != nullptr) {
-    fetch(V, vr, vr, 0);
-    for (int row0 = 0; row0 < vr; row0 += 32) {
-      stash();
-      __syncthreads();
-      if (row0 + 32 < vr) fetch(V, vr, vr, row0 + 32);
-      double o[4] = {0, 0, 0, 0};
-      for (int a = 0; a < JP; ++a) {
-        const double j = J[a][ob];
-        for (int q = 0; q < 4; ++q) o[q] += chunk[orr + q][a] * j;
-      }
-      for (int q = 0; q < 4; ++q) {
-        const int gr = row0 + orr + q;
-        if (gr < vr) V[(int64_t)col(ob) * vr + gr] = o[q];
-      }
-      __syncthreads();
-    }
   }
 }
 
@@ -400,6 +395,8 @@ __global__ __launch_bounds__(256) void jac_pick_kernel(const double* __restrict_
 // 1e-13 of the column's original norm nrm0 (recorded in dead[]), on the second
 // a unit column that keeps at most half its length after the re-projection.
 constexpr int TQ = 128;   // rows per chunk
+constexpr int OBW = 64;   // columns per orthonormalisation block
+constexpr int OBP = OBW + 1;
 
 __device__ __forceinline__ double block_sum256(double v, double* sh) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
@@ -413,22 +410,23 @@ __global__ __launch_bounds__(256) void tsqr_local_kernel(
     const double* __restrict__ src, int rows, int64_t lds, int nb, double* __restrict__ q,
     int64_t ldq, int qcols, double* __restrict__ r, int top, const double* __restrict__ nrm0,
     int c0, int* __restrict__ dead, int final, const int* __restrict__ healthy) {
-  __shared__ double T[TQ][33];
-  __shared__ double Rl[32][33];
-  __shared__ double red[8][33];
-  __shared__ double coef[32];
+  __shared__ double T[TQ][OBP];
+  __shared__ double Rl[OBW][OBP];
+  __shared__ double red[256 / OBW][OBP];
+  __shared__ double coef[OBW];
   __shared__ double sh[4];
   __shared__ int dep;
   if (*healthy) return;   // the Cholesky path took this block
   const int t = threadIdx.x;
   const int i0 = blockIdx.x * TQ;
-  for (int e = t; e < TQ * 32; e += 256) {
-    const int rr = e >> 5, cc = e & 31;
+  for (int e = t; e < TQ * OBW; e += 256) {
+    const int rr = e / OBW, cc = e % OBW;
     T[rr][cc] = (i0 + rr < rows && cc < nb) ? src[(int64_t)(i0 + rr) * lds + cc] : 0.0;
   }
-  for (int e = t; e < 32 * 33; e += 256) Rl[e / 33][e % 33] = 0.0;
+  for (int e = t; e < OBW * OBP; e += 256) Rl[e / OBP][e % OBP] = 0.0;
   __syncthreads();
-  const int ca = t & 31, cg = t >> 5;   // coefficient a, row group of 16
+  constexpr int NG = 256 / OBW, GR = TQ / NG;   // row groups for the coefficients
+  const int ca = t % OBW, cg = t / OBW;       // coefficient a, row group cg
   auto colsq = [&](int j) {
     const double v = (t < TQ) ? T[t][j] : 0.0;
     return block_sum256(v * v, sh);
@@ -437,12 +435,12 @@ __global__ __launch_bounds__(256) void tsqr_local_kernel(
   auto project = [&](int j, double w) {
     double pp = 0.0;
     if (ca < j)
-      for (int rr = cg * 16; rr < cg * 16 + 16; ++rr) pp += T[rr][ca] * T[rr][j];
+      for (int rr = cg * GR; rr < cg * GR + GR; ++rr) pp += T[rr][ca] * T[rr][j];
     red[cg][ca] = pp;
     __syncthreads();
     if (t < j) {
       double cs = 0.0;
-      for (int g = 0; g < 8; ++g) cs += red[g][t];
+      for (int g = 0; g < NG; ++g) cs += red[g][t];
       coef[t] = cs;
       Rl[t][j] += w * cs;
     }
@@ -491,39 +489,40 @@ __global__ __launch_bounds__(256) void tsqr_local_kernel(
     }
     __syncthreads();
   }
-  for (int e = t; e < TQ * 32; e += 256) {
-    const int rr = e >> 5, cc = e & 31;
+  for (int e = t; e < TQ * OBW; e += 256) {
+    const int rr = e / OBW, cc = e % OBW;
     if (i0 + rr < rows && cc < qcols) q[(int64_t)(i0 + rr) * ldq + cc] = T[rr][cc];
   }
   if (r != nullptr)
-    for (int e = t; e < 32 * 32; e += 256) {
-      const int rr = e >> 5, cc = e & 31;
-      r[((int64_t)blockIdx.x * 32 + rr) * 32 + cc] = Rl[rr][cc];
+    for (int e = t; e < OBW * OBW; e += 256) {
+      const int rr = e / OBW, cc = e % OBW;
+      r[((int64_t)blockIdx.x * OBW + rr) * OBW + cc] = Rl[rr][cc];
     }
 }
 
-// dst rows of chunk b = Q rows of chunk b (TQ x 32, ld 32) times W rows
-// [32 b, 32 b + 32) (ld 32); nb columns.
+// dst rows of chunk b = Q rows of chunk b (TQ x OBW, ld OBW) times W rows
+// [OBW b, OBW b + OBW) (ld OBW); nb columns.
 __global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restrict__ Q, int rows,
                                                          const double* __restrict__ W, int nb,
                                                          double* __restrict__ dst, int64_t ldd,
                                                          const int* __restrict__ healthy) {
-  __shared__ double Ws[32][33];
-  __shared__ double Qs[TQ][33];
+  __shared__ double Ws[OBW][OBP];
+  __shared__ double Qs[TQ][OBP];
   if (*healthy) return;
   const int t = threadIdx.x;
   const int i0 = blockIdx.x * TQ;
-  for (int e = t; e < 32 * 32; e += 256) Ws[e >> 5][e & 31] = W[((int64_t)blockIdx.x * 32 + (e >> 5)) * 32 + (e & 31)];
-  for (int e = t; e < TQ * 32; e += 256) {
-    const int rr = e >> 5, cc = e & 31;
-    Qs[rr][cc] = (i0 + rr < rows) ? Q[(int64_t)(i0 + rr) * 32 + cc] : 0.0;
+  for (int e = t; e < OBW * OBW; e += 256)
+    Ws[e / OBW][e % OBW] = W[((int64_t)blockIdx.x * OBW + e / OBW) * OBW + e % OBW];
+  for (int e = t; e < TQ * OBW; e += 256) {
+    const int rr = e / OBW, cc = e % OBW;
+    Qs[rr][cc] = (i0 + rr < rows) ? Q[(int64_t)(i0 + rr) * OBW + cc] : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < TQ * 32; e += 256) {
-    const int rr = e >> 5, cc = e & 31;
+  for (int e = t; e < TQ * OBW; e += 256) {
+    const int rr = e / OBW, cc = e % OBW;
     if (i0 + rr >= rows || cc >= nb) continue;
     double v = 0.0;
-    for (int a2 = 0; a2 < 32; ++a2) v += Qs[rr][a2] * Ws[a2][cc];
+    for (int a2 = 0; a2 < OBW; ++a2) v += Qs[rr][a2] * Ws[a2][cc];
     dst[(int64_t)(i0 + rr) * ldd + cc] = v;
   }
 }
@@ -545,14 +544,14 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restric
                                                          int* __restrict__ dead, int final,
                                                          double* __restrict__ Ri,
                                                          int* __restrict__ healthy) {
-  __shared__ double W[32][33];    // G, overwritten by the trailing updates
-  __shared__ double R[32][33];
-  __shared__ double X[32][33];    // R^{-1}
-  __shared__ double gd[32];       // diagonal of G
-  __shared__ int ok, isdead[32];
+  __shared__ double W[OBW][OBP];    // G, overwritten by the trailing updates
+  __shared__ double R[OBW][OBP];
+  __shared__ double X[OBW][OBP];    // R^{-1}
+  __shared__ double gd[OBW];        // diagonal of G
+  __shared__ int ok, isdead[OBW];
   const int t = threadIdx.x;
-  for (int e = t; e < 32 * 32; e += 256) {
-    const int i = e >> 5, j = e & 31;
+  for (int e = t; e < OBW * OBW; e += 256) {
+    const int i = e / OBW, j = e % OBW;
     W[i][j] = (i < nb && j < nb) ? G[i * nb + j] : 0.0;
     R[i][j] = 0.0;
     X[i][j] = (i == j && i < nb) ? 1.0 : 0.0;
@@ -635,8 +634,8 @@ __global__ __launch_bounds__(256) void apply_ri_kernel(double* __restrict__ U, i
                                                        int c0, int nb,
                                                        const double* __restrict__ Ri,
                                                        const int* __restrict__ healthy) {
-  __shared__ double Rs[32][33];
-  __shared__ double P[64][33];
+  __shared__ double Rs[OBW][OBP];
+  __shared__ double P[64][OBP];
   if (!*healthy) return;
   const int t = threadIdx.x;
   const int i0 = blockIdx.x * 64;
@@ -731,13 +730,13 @@ void tsqr_fallback(Ctx& c, double* A, int m, int kk, int c0, int nbk, const doub
   for (;;) {
     const int chunks = (rows + TQ - 1) / TQ;
     const bool top = chunks == 1;
-    double* q = top && qs.empty() ? A + c0 : (double*)c.arena.alloc(sizeof(double) * (size_t)rows * 32);
-    const int64_t ldq = top && qs.empty() ? kk : 32;
-    double* r = top ? nullptr : (double*)c.arena.alloc(sizeof(double) * (size_t)chunks * 32 * 32);
+    double* q = top && qs.empty() ? A + c0 : (double*)c.arena.alloc(sizeof(double) * (size_t)rows * OBW);
+    const int64_t ldq = top && qs.empty() ? kk : OBW;
+    double* r = top ? nullptr : (double*)c.arena.alloc(sizeof(double) * (size_t)chunks * OBW * OBW);
     if (!c.dry) {
       ProfScope ps(c, K_SVD_OTHER, 6.0 * rows * nbk * nbk, 8.0 * 2.0 * rows * nbk);
-      // scratch Q factors carry all 32 columns (zeros beyond nbk)
-      const int qcols = (q == A + c0) ? nbk : 32;
+      // scratch Q factors carry all OBW columns (zeros beyond nbk)
+      const int qcols = (q == A + c0) ? nbk : OBW;
       hipLaunchKernelGGL(tsqr_local_kernel, dim3(chunks), dim3(256), 0, c.stream, src, rows, lds,
                          nbk, q, ldq, qcols, r, top ? 1 : 0, nrm0, c0, dead, pass, healthy);
       c.check_launch();
@@ -746,18 +745,18 @@ void tsqr_fallback(Ctx& c, double* A, int m, int kk, int c0, int nbk, const doub
     rws.push_back(rows);
     if (top) break;
     src = r;
-    lds = 32;
-    rows = chunks * 32;
+    lds = OBW;
+    rows = chunks * OBW;
   }
   // multiply back down: W_l = Q_l W_{l+1}; the last product lands in A
   const double* W = qs.back();
   for (int l = (int)qs.size() - 2; l >= 0; --l) {
-    double* out = (l == 0) ? A + c0 : (double*)c.arena.alloc(sizeof(double) * (size_t)rws[l] * 32);
-    const int64_t ldo = (l == 0) ? kk : 32;
+    double* out = (l == 0) ? A + c0 : (double*)c.arena.alloc(sizeof(double) * (size_t)rws[l] * OBW);
+    const int64_t ldo = (l == 0) ? kk : OBW;
     if (!c.dry) {
-      ProfScope ps(c, K_SVD_OTHER, 2.0 * rws[l] * 32.0 * nbk, 8.0 * 3.0 * rws[l] * 32);
+      ProfScope ps(c, K_SVD_OTHER, 2.0 * rws[l] * (double)OBW * nbk, 8.0 * 3.0 * rws[l] * OBW);
       hipLaunchKernelGGL(tsqr_apply_kernel, dim3((rws[l] + TQ - 1) / TQ), dim3(256), 0, c.stream,
-                         qs[l], rws[l], W, (l == 0) ? nbk : 32, out, ldo, healthy);
+                         qs[l], rws[l], W, (l == 0) ? nbk : OBW, out, ldo, healthy);
       c.check_launch();
     }
     W = out;
@@ -775,8 +774,8 @@ void tsqr_fallback(Ctx& c, double* A, int m, int kk, int c0, int nbk, const doub
 // block, is still made orthogonal to the earlier blocks.  Columns dependent
 // to working precision come out as zero columns: the nonzero columns are
 // orthonormal and span the columns of A up to rounding.
-void orthonormalize(Ctx& c, double* A, int m, int kk) {
-  constexpr int OB = 32;
+void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
+  constexpr int OB = OBW;
   const size_t mk = c.arena.mark();
   const int rows = 64;
   const int chunks = (m + rows - 1) / rows;
@@ -797,7 +796,7 @@ void orthonormalize(Ctx& c, double* A, int m, int kk) {
   }
   for (int c0 = 0; c0 < kk; c0 += OB) {
     const int nbk = std::min(OB, kk - c0);
-    for (int pass = 0; pass < 2; ++pass) {
+    for (int pass = 0; pass < rounds; ++pass) {
       if (c0 > 0) {
         gemm(c, F64, c0, nbk, m, 1.0, A, kk, 1, A + c0, kk, 0, 0.0, G, nbk);
         gemm(c, F64, m, nbk, c0, -1.0, A, kk, 0, G, nbk, 0, 1.0, A + c0, kk);
@@ -902,6 +901,13 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
       }
       hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(1), 0, c.stream, flags);
     }
+    if (std::getenv("CTM_DEBUG_SWEEPS")) {   // diagnostics only: blocks the host
+      int f[3] = {0, 0, 0};
+      c.check(hipMemcpyAsync(f, flags, sizeof(f), hipMemcpyDeviceToHost, c.stream));
+      c.check(hipStreamSynchronize(c.stream));
+      std::fprintf(stderr, "tsvd_core m=%d n=%d: %d rotating sweeps, converged %d\n", m, n, f[2],
+                   f[0]);
+    }
     ProfScope ps(c, K_SVD_OTHER, 0.0, 8.0 * (double)r * cp + 16.0 * (double)n * kk);
     hipLaunchKernelGGL(jac_colnorm_kernel, dim3(cp), dim3(256), 0, c.stream, X, r, cp, sig);
     hipLaunchKernelGGL(jac_rank_kernel, dim3((cp + 255) / 256), dim3(256), 0, c.stream, sig, cp,
@@ -939,7 +945,7 @@ void tsvd_wide(Ctx& c, const double* M, int m, int n, int k, double tau, double*
 // Dispatch: large problems are first narrowed to a small factor whose SVD the
 // preconditioned Jacobi method then takes.
 //  - 128 <= k <= min(m, n) / 4 with min(m, n) >= 768: randomised range finder
-//    with two power iterations (subspace of b = k + p columns,
+//    with one power iteration (subspace of b = k + p columns,
 //    p = max(32, k / 4), Gaussian test matrix from a counter-based generator);
 //    with Y = Q the range basis, B = Q^T M is wide and B^T = M^T Q; then
 //    L = B Q_B from the QR of B^T is b x b with the left singular vectors of
@@ -965,10 +971,12 @@ void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, d
       c.check_launch();
     }
     gemm(c, F64, m, b, n, 1.0, M, n, 0, Z, b, 0, 0.0, Y, b);            // Y = M Om
-    for (int it = 0; it < 2; ++it) {
-      orthonormalize(c, Y, m, b);
+    // one power step; it only needs a well-conditioned basis: one
+    // Gram-Schmidt round (orthogonal to ~1e-4 at worst) instead of two
+    for (int it = 0; it < 1; ++it) {
+      orthonormalize(c, Y, m, b, 1);
       gemm(c, F64, n, b, m, 1.0, M, n, 1, Y, b, 0, 0.0, Z, b);          // Z = M^T Y
-      orthonormalize(c, Z, n, b);
+      orthonormalize(c, Z, n, b, 1);
       gemm(c, F64, m, b, n, 1.0, M, n, 0, Z, b, 0, 0.0, Y, b);          // Y = M Z
     }
     orthonormalize(c, Y, m, b);                              // Q

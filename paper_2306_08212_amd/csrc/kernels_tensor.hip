@@ -348,6 +348,35 @@ void permute(Ctx& c, const Tensor& in, const int* perm, Tensor& out, double scal
 #undef CTM_PERM
 }
 
+__global__ __launch_bounds__(256) void copy_u64_kernel(uint64_t* __restrict__ dst,
+                                                       const uint64_t* __restrict__ src, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(256) void copy_u8_kernel(unsigned char* __restrict__ dst,
+                                                      const unsigned char* __restrict__ src,
+                                                      int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dst[i] = src[i];
+}
+
+// Device-to-device copy as a kernel (a plain kernel node when captured).
+void copy_bytes(Ctx& c, void* dst, const void* src, size_t bytes) {
+  if (c.dry || bytes == 0) return;
+  const bool w8 = bytes % 8 == 0 && ((uintptr_t)dst % 8) == 0 && ((uintptr_t)src % 8) == 0;
+  const int64_t n = w8 ? (int64_t)(bytes / 8) : (int64_t)bytes;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (w8)
+    hipLaunchKernelGGL(copy_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, c.stream,
+                       (uint64_t*)dst, (const uint64_t*)src, n);
+  else
+    hipLaunchKernelGGL(copy_u8_kernel, dim3((unsigned)blocks), dim3(256), 0, c.stream,
+                       (unsigned char*)dst, (const unsigned char*)src, n);
+  c.check_launch();
+}
+
 void fill(Ctx& c, void* p, int dt, int64_t n, double v) {
   if (c.dry || n <= 0) return;
   int64_t blocks = (n + 255) / 256;

@@ -132,8 +132,8 @@ def test_tsvd_matches_oracle_truncate(name, make, k):
 
 @pytest.mark.parametrize("m,n,k", [(1100, 1200, 128), (2048, 2048, 256)])
 def test_tsvd_randomized_range(m, n, k):
-    """Large problems go through the randomised range finder (two power
-    iterations, k + max(32, k/4) columns): the top half of the spectrum to
+    """Large problems go through the randomised range finder (one power
+    iteration, k + max(32, k/4) columns): the top half of the spectrum to
     1e-12, the truncation residual within 1e-6 of the optimum, U orthonormal."""
     log("tsvd randomized", m, n, k)
     M = _graded(m, n, 0.9 ** (256.0 / k), 11)

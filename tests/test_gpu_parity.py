@@ -242,3 +242,4 @@ def test_config2_well_determined_cutoff(method):
     log("config2 tau rel err", np.max(np.abs(np.array(eb) - r["e_bond"]) / np.abs(r["e_bond"])))
     np.testing.assert_allclose(eb, r["e_bond"], rtol=1e-10)
     s.close()
+
