@@ -127,6 +127,17 @@ int ctm_set_env(ctm_solver *s, int e, const double *host_in, int p, int q);
 /* Moves done so far. */
 int ctm_moves_done(const ctm_solver *s);
 
+/* Graph replay of moves (default on).  The independent branches of a move
+ * (the side isometries and anchors of an insertion, the updates of its two
+ * rows) each run on a stream of their own; a branch whose launch sequence
+ * (fixed by direction, bond dimensions, method, precision, bootstrap state
+ * and its place in the move) comes up a second time is captured into a HIP
+ * graph and replayed from then on, so branches still overlap and the host
+ * issues a handful of calls per branch instead of one per kernel.  Results
+ * are bitwise those of eager launches.  ctm_set_graphs(s, 0) runs every move
+ * eagerly; either call synchronises the stream and frees the captured
+ * graphs.  Moves run eagerly while the profiler is on. */
+int ctm_set_graphs(ctm_solver *s, int enable);
 
 /* Switch the precision of the absorption chains (enum ctm_precision) for the
  * moves that follow; the environment is kept. */

@@ -27,7 +27,7 @@ PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
 METHODS = {"standard": STANDARD, "reduced": REDUCED}
 
 EXPORTS = ["ctm_workspace_size", "ctm_init", "ctm_move", "ctm_iterate", "ctm_converge",
-           "ctm_iterate_delta", "ctm_read_delta", "ctm_energy", "ctm_get_env", "ctm_set_env", "ctm_moves_done", "ctm_set_precision",
+           "ctm_iterate_delta", "ctm_read_delta", "ctm_energy", "ctm_get_env", "ctm_set_env", "ctm_moves_done", "ctm_set_precision", "ctm_set_graphs",
            "ctm_profile", "ctm_profile_read", "ctm_destroy",
            "ctm_status_string", "ctm_kernel_gemm", "ctm_kernel_tsvd", "ctm_kernel_tsvd_workspace",
            "ctm_kernel_permute"]
@@ -86,6 +86,8 @@ def load(path: str = LIB_PATH):
     lib.ctm_moves_done.restype = I
     lib.ctm_set_precision.argtypes = [P, I]
     lib.ctm_set_precision.restype = I
+    lib.ctm_set_graphs.argtypes = [P, I]
+    lib.ctm_set_graphs.restype = I
     lib.ctm_profile.argtypes = [P, I]
     lib.ctm_profile.restype = I
     lib.ctm_profile_read.argtypes = [P, I, ctypes.POINTER(ctypes.c_longlong),
@@ -243,6 +245,9 @@ class Solver:
     def set_precision(self, precision: int):
         _check(load().ctm_set_precision(self.handle, precision), "ctm_set_precision")
         self.cfg.precision = precision
+
+    def set_graphs(self, enable: bool):
+        _check(load().ctm_set_graphs(self.handle, int(enable)), "ctm_set_graphs")
 
     def profile(self, enable: bool):
         _check(load().ctm_profile(self.handle, int(enable)), "ctm_profile")

@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <new>
 #include <exception>
 #include <stdexcept>
@@ -47,7 +48,20 @@ struct ctm_solver {
   hipStream_t aux[kAux] = {};
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kMaxBranch] = {};
+  // moves replayed from captured HIP graphs, keyed by everything the launch
+  // sequence of a move depends on (see run_move)
+  bool graphs = true;
+  std::string move_tag;   // key of the move being issued ("" = no replay)
+  int branch_call = 0;    // run_branches calls so far in that move
+  std::map<std::string, hipGraphExec_t> gexec;
+  std::map<std::string, int> gseen;
+  void drop_graphs() {
+    for (auto& kv : gexec) (void)hipGraphExecDestroy(kv.second);
+    gexec.clear();
+    gseen.clear();
+  }
   ~ctm_solver() {
+    drop_graphs();
     for (hipStream_t& st : aux)
       if (st) (void)hipStreamDestroy(st);
     if (ev_fork) (void)hipEventDestroy(ev_fork);
@@ -140,17 +154,62 @@ void run_branches(ctm_solver* s, const std::vector<std::function<void(Ctx&)>>& f
     k.arena.cap = need[b];
     k.rng_calls = r0 + 64 * (uint64_t)(b + 1);
   }
-  // each branch is issued from its own host thread (kernel launches cost
-  // host time, and the branches share no host state); with the profiler on
-  // they are issued in order from this thread
+  // A branch whose key (the move's key, this fork point and the branch) has
+  // come up before is captured into a HIP graph on its stream and replayed
+  // from then on: the branch function then runs in dry mode over the same
+  // workspace slice, which reproduces its host-side results (shapes and
+  // buffer addresses of its outputs) without a launch.  The fork and join
+  // stay eager, so replayed branches still run concurrently.
+  const bool replay = par && !s->move_tag.empty() && c.prof == nullptr;
+  const int call = s->branch_call++;
   auto issue = [&](int b) {
     Ctx& k = ks[b];
     if (par) k.check(hipStreamWaitEvent(k.stream, s->ev_fork, 0));
-    fs[b](k);
+    hipGraphExec_t ex = nullptr;
+    std::string key;
+    if (replay) {
+      key = s->move_tag + "#" + std::to_string(call) + "." + std::to_string(b);
+      auto it = s->gexec.find(key);
+      if (it != s->gexec.end()) ex = it->second;
+    }
+    if (ex != nullptr) {
+      k.dry = true;
+      fs[b](k);
+      k.dry = false;
+      k.check(hipGraphLaunch(ex, k.stream));
+    } else if (replay && s->gseen[key] >= 1) {
+      hipGraph_t g = nullptr;
+      k.check(hipStreamBeginCapture(k.stream, hipStreamCaptureModeRelaxed));
+      try {
+        fs[b](k);
+      } catch (...) {
+        (void)hipStreamEndCapture(k.stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+      }
+      k.check(hipStreamEndCapture(k.stream, &g));
+      if (g != nullptr && k.hip_err == hipSuccess) k.check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
+      if (g) (void)hipGraphDestroy(g);
+      if (ex == nullptr) throw std::runtime_error("branch capture failed");
+      s->gexec[key] = ex;
+      k.check(hipGraphLaunch(ex, k.stream));
+    } else {
+      if (replay) s->gseen[key] += 1;
+      fs[b](k);
+    }
     if (par) k.check(hipEventRecord(s->ev_join[b], k.stream));
   };
+  // each branch is issued from its own host thread (kernel launches cost
+  // host time, and the branches share no host state); with the profiler on,
+  // or when a branch is captured or seen for the first time (the graph maps
+  // are shared), they are issued in order from this thread
+  bool threads = par && c.prof == nullptr && n > 1;
+  if (replay)
+    for (int b = 0; b < n && threads; ++b)
+      if (!s->gexec.count(s->move_tag + "#" + std::to_string(call) + "." + std::to_string(b)))
+        threads = false;
   std::vector<std::exception_ptr> errs(n);
-  if (par && c.prof == nullptr && n > 1) {
+  if (threads) {
     std::vector<std::thread> th;
     for (int b = 1; b < n; ++b)
       th.emplace_back([&, b] {
@@ -462,9 +521,34 @@ void do_move(ctm_solver* s, int r) {
   s->moves++;
 }
 
+// Everything the launch sequence of a move in frame r depends on: the
+// schedule follows from the bond dimensions, method, precision and bootstrap
+// state alone; buffers sit at fixed places in the workspace and the random
+// test matrices depend only on their position in the move.
+std::string move_key(const ctm_solver* s, int r) {
+  std::string k = std::to_string(r) + "/" + std::to_string(s->precision) + "/" +
+                  std::to_string(s->method) + "/" + std::to_string(s->moves / 4 < s->boot_iters);
+  for (int e = 0; e < 16; ++e) k += "/" + std::to_string(s->pd[e]) + "x" + std::to_string(s->qd[e]);
+  return k;
+}
+
+// One move.  With graph replay on, the concurrent branches of the move are
+// captured and replayed per branch (see run_branches) under the move's key.
+void run_move(ctm_solver* s, int r) {
+  s->move_tag = (s->graphs && s->ctx.prof == nullptr) ? move_key(s, r) : std::string();
+  s->branch_call = 0;
+  try {
+    do_move(s, r);
+  } catch (...) {
+    s->move_tag.clear();
+    throw;
+  }
+  s->move_tag.clear();
+}
+
 void do_iteration(ctm_solver* s) {
   static const int order[4] = {CTM_LEFT, CTM_RIGHT, CTM_UP, CTM_DOWN};
-  for (int i = 0; i < 4; ++i) do_move(s, order[i]);
+  for (int i = 0; i < 4; ++i) run_move(s, order[i]);
 }
 
 // normalised corner spectra of the 8 corners into spec[cur]
@@ -730,7 +814,7 @@ int ctm_init(const ctm_config* cfg, const double* A, const double* B, int ptrs_o
 int ctm_move(ctm_solver* s, int dir) {
   if (!s || dir < 0 || dir > 3) return CTM_EINVAL;
   try {
-    do_move(s, dir);
+    run_move(s, dir);
   } catch (...) {
     return CTM_EINVAL;
   }
@@ -895,6 +979,14 @@ int ctm_set_precision(ctm_solver* s, int precision) {
   // buffers were sized for FP64, the widest type
   s->precision = precision;
   rebuild_chain_sites(s);
+  return status_from(s);
+}
+
+int ctm_set_graphs(ctm_solver* s, int enable) {
+  if (!s) return CTM_EINVAL;
+  s->ctx.check(hipStreamSynchronize(s->ctx.stream));
+  s->drop_graphs();
+  s->graphs = enable != 0;
   return status_from(s);
 }
 

@@ -52,6 +52,7 @@ namespace {
 constexpr int JW = 16;         // columns per block
 constexpr int JP = 2 * JW;     // columns per pair
 constexpr double kSignTie = 1e-8;
+typedef double d4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void rr_pair(int nb, int round, int i, int* a, int* b) {
   // circle method: block 0 fixed, the others rotate
@@ -71,73 +72,72 @@ __device__ __forceinline__ bool needs_rotation(double app, double aqq, double ap
 // matrix G, at most max_sweeps sweeps; J accumulates the rotations.
 // Rutishauser's update of the pivot entries (a_pp - t a_pq, a_qq + t a_pq,
 // a_pq = 0) keeps small entries relatively accurate.
+//
+// One step applies the 16 disjoint rotations of a round-robin round as
+// G <- J^T G J.  Thread t owns the 2 x 2 block of G at the rows of pair t/16
+// and the columns of pair t%16, and two rows of J's columns of pair t/16;
+// it computes both rotations it needs from the pivot entries itself, so a
+// step is one read phase and one write phase (rows first, then columns, the
+// same order of operations as a row pass followed by a column pass).
+__device__ __forceinline__ bool jac_rotation(double app, double aqq, double apq, double tol,
+                                             double gnoise, double thr, double* c, double* s,
+                                             double* tt) {
+  *c = 1.0;
+  *s = 0.0;
+  *tt = 0.0;
+  if (!needs_rotation(app, aqq, apq, tol, gnoise, thr)) return false;
+  const double tau = (aqq - app) / (2.0 * apq);
+  *tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  *c = 1.0 / sqrt(1.0 + *tt * *tt);
+  *s = *tt * *c;
+  return true;
+}
+
 __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double tol,
-                               double gnoise, double thr, int max_sweeps, int* sflag,
-                               double* cs, int* pq) {
+                               double gnoise, double thr, int max_sweeps, int* sflag) {
   const int t = threadIdx.x;
-  __shared__ double piv[JP / 2][3];
   for (int idx = t; idx < JP * JP; idx += blockDim.x) J[idx / JP][idx % JP] = (idx / JP == idx % JP) ? 1.0 : 0.0;
+  const int bi = t >> 4, bj = t & 15;   // pair of the rows / of the columns
+  const int jr = (t & 15) * 2;          // rows of J this thread rotates
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     if (t == 0) *sflag = 0;
     __syncthreads();
     for (int round = 0; round < JP - 1; ++round) {
-      if (t < JP / 2) {
-        int p, q;
-        rr_pair(JP, round, t, &p, &q);
-        if (p > q) { const int x = p; p = q; q = x; }
-        const double app = G[p][p], aqq = G[q][q], apq = G[p][q];
-        double c = 1.0, s = 0.0, tt = 0.0;
-        if (needs_rotation(app, aqq, apq, tol, gnoise, thr)) {
-          const double tau = (aqq - app) / (2.0 * apq);
-          tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + tt * tt);
-          s = tt * c;
-          *sflag = 1;
+      int pi, qi, pj, qj;
+      rr_pair(JP, round, bi, &pi, &qi);
+      if (pi > qi) { const int x = pi; pi = qi; qi = x; }
+      rr_pair(JP, round, bj, &pj, &qj);
+      if (pj > qj) { const int x = pj; pj = qj; qj = x; }
+      const double app = G[pi][pi], aqq = G[qi][qi], apq = G[pi][qi];
+      const double bpp = G[pj][pj], bqq = G[qj][qj], bpq = G[pj][qj];
+      const double b00 = G[pi][pj], b01 = G[pi][qj], b10 = G[qi][pj], b11 = G[qi][qj];
+      const double j00 = J[jr][pi], j01 = J[jr][qi], j10 = J[jr + 1][pi], j11 = J[jr + 1][qi];
+      double ci, si, ti, cj, sj, tj;
+      const bool roti = jac_rotation(app, aqq, apq, tol, gnoise, thr, &ci, &si, &ti);
+      jac_rotation(bpp, bqq, bpq, tol, gnoise, thr, &cj, &sj, &tj);
+      __syncthreads();   // every read of this step precedes every write
+      if (bi == bj) {
+        if (roti) {
+          G[pi][pi] = app - ti * apq;
+          G[qi][qi] = aqq + ti * apq;
+          G[pi][qi] = 0.0;
+          G[qi][pi] = 0.0;
         }
-        cs[2 * t] = c;
-        cs[2 * t + 1] = s;
-        pq[2 * t] = p;
-        pq[2 * t + 1] = q;
-        piv[t][0] = app - tt * apq;
-        piv[t][1] = aqq + tt * apq;
+      } else {
+        const double r00 = ci * b00 - si * b10, r01 = ci * b01 - si * b11;
+        const double r10 = si * b00 + ci * b10, r11 = si * b01 + ci * b11;
+        G[pi][pj] = cj * r00 - sj * r01;
+        G[pi][qj] = sj * r00 + cj * r01;
+        G[qi][pj] = cj * r10 - sj * r11;
+        G[qi][qj] = sj * r10 + cj * r11;
       }
-      __syncthreads();
-      // rows: G <- J^T G, and the pivot 2x2 blocks set exactly (no update
-      // of either phase touches them)
-      for (int task = t; task < (JP / 2) * JP; task += blockDim.x) {
-        const int i = task / JP, k = task % JP;
-        const int p = pq[2 * i], q = pq[2 * i + 1];
-        const double c = cs[2 * i], s = cs[2 * i + 1];
-        if (s != 0.0 && k != p && k != q) {
-          const double gp = G[p][k], gq = G[q][k];
-          G[p][k] = c * gp - s * gq;
-          G[q][k] = s * gp + c * gq;
-        }
-      }
-      if (t < JP / 2 && cs[2 * t + 1] != 0.0) {
-        const int p = pq[2 * t], q = pq[2 * t + 1];
-        G[p][p] = piv[t][0];
-        G[q][q] = piv[t][1];
-        G[p][q] = 0.0;
-        G[q][p] = 0.0;
-      }
-      __syncthreads();
-      // columns: G <- G J, J <- J J
-      for (int task = t; task < (JP / 2) * JP; task += blockDim.x) {
-        const int i = task / JP, k = task % JP;
-        const int p = pq[2 * i], q = pq[2 * i + 1];
-        const double c = cs[2 * i], s = cs[2 * i + 1];
-        if (s != 0.0) {
-          if (k != p && k != q) {
-            const double gp = G[k][p], gq = G[k][q];
-            G[k][p] = c * gp - s * gq;
-            G[k][q] = s * gp + c * gq;
-          }
-          const double jp = J[k][p], jq = J[k][q];
-          J[k][p] = c * jp - s * jq;
-          J[k][q] = s * jp + c * jq;
-        }
+      if (roti) {
+        J[jr][pi] = ci * j00 - si * j01;
+        J[jr][qi] = si * j00 + ci * j01;
+        J[jr + 1][pi] = ci * j10 - si * j11;
+        J[jr + 1][qi] = si * j10 + ci * j11;
+        if (bj == 0) *sflag = 1;
       }
       __syncthreads();
     }
@@ -148,19 +148,28 @@ __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double 
 
 // One round of the block tournament.  X: r rows, ld = ldx, column-major.
 // V: vr rows (0 = none), ld = vr.  fro: ||X||_F on the device.
+// The 32 columns of a block pair pass through LDS in chunks of CH rows; the
+// Gram matrix and the rotation of the columns are FP64 matrix-core products
+// (v_mfma_f64_16x16x4f64: operand lane l holds row l%16 / column l%16 at
+// k = l/16; result lane l, element i is row l/16 + 4 i, column l%16).
+constexpr int CH = 64;
+
 __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, int r, int64_t ldx,
                                                         double* __restrict__ V, int vr, int nb,
                                                         int round, double tol, double tol_in,
                                                         int inner_sweeps,
                                                         const double* __restrict__ fro,
                                                         int* __restrict__ flags,
-                                                        double* __restrict__ work) {
+                                                        double* __restrict__ work, int xslot) {
   __shared__ double G[JP][JP + 1];
   __shared__ double J[JP][JP + 1];
-  __shared__ double chunk[32][JP + 1];
-  __shared__ double cs[JP];
-  __shared__ int pq[JP];
+  __shared__ double chunk[CH][JP + 1];
+  __shared__ double outc[CH][JP + 1];
   __shared__ int any, sflag;
+  // workgroups go to the 8 XCDs round robin; only those of XCD xslot work,
+  // so every round of one SVD finds X and V in the same L2
+  if ((int)(blockIdx.x & 7) != xslot) return;
+  const int pair = blockIdx.x >> 3;
   if (flags[0]) return;   // converged in an earlier sweep
   // columns below the rounding noise of the rotations (norm < 2 sqrt(r) eps
   // ||M||_F) are not made orthogonal: their directions are not determined by
@@ -168,57 +177,57 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
   const double gnoise = 4.0 * (double)r * 4.930380657631324e-32 * fro[0] * fro[0];
   const double thr = 4.0 * 2.220446049250313e-16 * fro[0];
   int bi, bj;
-  rr_pair(nb, round, blockIdx.x, &bi, &bj);
-  const int t = threadIdx.x;
+  rr_pair(nb, round, pair, &bi, &bj);
+  const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
   auto col = [&](int a) { return a < JW ? bi * JW + a : bj * JW + (a - JW); };
 
-  // Gram of the 32 columns; chunks of 32 rows go through LDS, the next one
-  // is fetched into registers while the current one is used
-  const int ga = t >> 3, gb = (t & 7) * 4;
-  double g0 = 0, g1 = 0, g2 = 0, g3 = 0;
-  double pre[4];
+  constexpr int PER = CH * JP / 256;   // doubles per thread and chunk
+  double pre[PER];
   auto fetch = [&](const double* src, int rows, int64_t ld, int row0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < PER; ++q) {
       const int e = t + 256 * q;
-      const int a = e >> 5, rr = e & 31;
+      const int a = e / CH, rr = e % CH;
       const int gr = row0 + rr;
       pre[q] = gr < rows ? src[(int64_t)col(a) * ld + gr] : 0.0;
     }
   };
   auto stash = [&]() {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < PER; ++q) {
       const int e = t + 256 * q;
-      chunk[e & 31][e >> 5] = pre[q];
+      chunk[e % CH][e / CH] = pre[q];
     }
   };
+
+  // Gram: wave w computes the 16 x 16 tile (w / 2, w % 2)
+  const int mt = wave >> 1, nt = wave & 1;
+  d4 gacc = {0.0, 0.0, 0.0, 0.0};
   fetch(X, r, ldx, 0);
-  for (int row0 = 0; row0 < r; row0 += 32) {
+  for (int row0 = 0; row0 < r; row0 += CH) {
     stash();
     __syncthreads();
-    if (row0 + 32 < r) fetch(X, r, ldx, row0 + 32);
-#pragma unroll 8
-    for (int rr = 0; rr < 32; ++rr) {
-      const double x = chunk[rr][ga];
-      g0 += x * chunk[rr][gb];
-      g1 += x * chunk[rr][gb + 1];
-      g2 += x * chunk[rr][gb + 2];
-      g3 += x * chunk[rr][gb + 3];
+    if (row0 + CH < r) fetch(X, r, ldx, row0 + CH);
+#pragma unroll
+    for (int kk = 0; kk < CH; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      gacc = __builtin_amdgcn_mfma_f64_16x16x4f64(chunk[kr][mt * 16 + (lane & 15)],
+                                                  chunk[kr][nt * 16 + (lane & 15)], gacc, 0, 0, 0);
     }
     __syncthreads();
   }
-  G[ga][gb] = g0;
-  G[ga][gb + 1] = g1;
-  G[ga][gb + 2] = g2;
-  G[ga][gb + 3] = g3;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) G[mt * 16 + (lane >> 4) + 4 * q][nt * 16 + (lane & 15)] = gacc[q];
   if (t == 0) any = 0;
   __syncthreads();
-  for (int q = 0; q < 4; ++q) {
-    const int b = gb + q;
-    if (b != ga) {
-      const double gab = G[ga][b], gaa = G[ga][ga], gbb = G[b][b];
-      if (needs_rotation(gaa, gbb, gab, tol, gnoise, thr)) any = 1;
+  {
+    const int ga = t >> 3, gb = (t & 7) * 4;
+    for (int q = 0; q < 4; ++q) {
+      const int b = gb + q;
+      if (b != ga) {
+        const double gab = G[ga][b], gaa = G[ga][ga], gbb = G[b][b];
+        if (needs_rotation(gaa, gbb, gab, tol, gnoise, thr)) any = 1;
+      }
     }
   }
   __syncthreads();
@@ -231,37 +240,48 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
     atomicAdd(&work[1], 8.0 * JP * (r + rot * 2.0 * (r + vr)));
   }
   if (!any) return;
-  lds_sym_jacobi(G, J, tol_in, gnoise, thr, inner_sweeps, &sflag, cs, pq);
+  lds_sym_jacobi(G, J, tol_in, gnoise, thr, inner_sweeps, &sflag);
   if (t == 0) atomicAdd(&flags[1], 1);
 
-  // [X; V][:, cols] <- [X; V][:, cols] J, as one stream of 32-row chunks over
-  // the rows of X and then of V (thread: column b = t/8, 4 consecutive rows)
-  const int ob = t >> 3, orr = (t & 7) * 4;
-  const int nx = (r + 31) / 32, nv = (V != nullptr) ? (vr + 31) / 32 : 0;
+  // [X; V][:, cols] <- [X; V][:, cols] J, as one stream of CH-row chunks over
+  // the rows of X and then of V.  Wave w forms row tiles 2 (w / 2) and
+  // 2 (w / 2) + 1 of column tile w % 2; its slice of J stays in registers.
+  double jb[JP / 4];
+#pragma unroll
+  for (int q = 0; q < JP / 4; ++q) jb[q] = J[4 * q + (lane >> 4)][nt * 16 + (lane & 15)];
+  const int nx = (r + CH - 1) / CH, nv = (V != nullptr) ? (vr + CH - 1) / CH : 0;
   auto fetch_chunk = [&](int ci) {
-    if (ci < nx) fetch(X, r, ldx, ci * 32);
-    else fetch(V, vr, vr, (ci - nx) * 32);
+    if (ci < nx) fetch(X, r, ldx, ci * CH);
+    else fetch(V, vr, vr, (ci - nx) * CH);
   };
   fetch_chunk(0);
   for (int ci = 0; ci < nx + nv; ++ci) {
     stash();
     __syncthreads();
     if (ci + 1 < nx + nv) fetch_chunk(ci + 1);
-    double o[4] = {0, 0, 0, 0};
-    for (int a = 0; a < JP; ++a) {
-      const double j = J[a][ob];
-      for (int q = 0; q < 4; ++q) o[q] += chunk[orr + q][a] * j;
+#pragma unroll
+    for (int i2 = 0; i2 < 2; ++i2) {
+      const int m2 = (wave >> 1) * 2 + i2;
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q = 0; q < JP / 4; ++q)
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(chunk[m2 * 16 + (lane & 15)][4 * q + (lane >> 4)],
+                                                   jb[q], acc, 0, 0, 0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) outc[m2 * 16 + (lane >> 4) + 4 * q][nt * 16 + (lane & 15)] = acc[q];
     }
+    __syncthreads();
     const bool isx = ci < nx;
-    const int row0 = isx ? ci * 32 : (ci - nx) * 32;
+    const int row0 = isx ? ci * CH : (ci - nx) * CH;
     const int rows = isx ? r : vr;
     double* dst = isx ? X : V;
     const int64_t ld = isx ? ldx : (int64_t)vr;
-    for (int q = 0; q < 4; ++q) {
-      const int gr = row0 + orr + q;
-      if (gr < rows) dst[(int64_t)col(ob) * ld + gr] = o[q];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = t + 256 * q;
+      const int a = e / CH, rr = e % CH;
+      if (row0 + rr < rows) dst[(int64_t)col(a) * ld + row0 + rr] = outc[rr][a];
     }
-    __syncthreads();
   }
 }
 
@@ -383,7 +403,7 @@ __global__ __launch_bounds__(256) void jac_pick_kernel(const double* __restrict_
 }
 
 // Gram-Schmidt fallback of the in-block step, as a tree (TSQR): the block's
-// rows are cut into chunks of 128; each workgroup orthonormalises its chunk in
+// rows are cut into chunks of 256; each workgroup orthonormalises its chunk in
 // LDS (classical Gram-Schmidt twice, then a third projection that checks the
 // normalised column: if it loses more than half its length, the column was
 // rounding noise and is dependent), keeping the projection coefficients as
@@ -394,7 +414,7 @@ __global__ __launch_bounds__(256) void jac_pick_kernel(const double* __restrict_
 // dependence follows the block rules: on the first visit a residual at most
 // 1e-13 of the column's original norm nrm0 (recorded in dead[]), on the second
 // a unit column that keeps at most half its length after the re-projection.
-constexpr int TQ = 128;   // rows per chunk
+constexpr int TQ = 256;   // rows per chunk
 constexpr int OBW = 64;   // columns per orthonormalisation block
 constexpr int OBP = OBW + 1;
 
@@ -411,7 +431,6 @@ __global__ __launch_bounds__(256) void tsqr_local_kernel(
     int64_t ldq, int qcols, double* __restrict__ r, int top, const double* __restrict__ nrm0,
     int c0, int* __restrict__ dead, int final, const int* __restrict__ healthy) {
   __shared__ double T[TQ][OBP];
-  __shared__ double Rl[OBW][OBP];
   __shared__ double red[256 / OBW][OBP];
   __shared__ double coef[OBW];
   __shared__ double sh[4];
@@ -423,38 +442,55 @@ __global__ __launch_bounds__(256) void tsqr_local_kernel(
     const int rr = e / OBW, cc = e % OBW;
     T[rr][cc] = (i0 + rr < rows && cc < nb) ? src[(int64_t)(i0 + rr) * lds + cc] : 0.0;
   }
-  for (int e = t; e < OBW * OBP; e += 256) Rl[e / OBP][e % OBP] = 0.0;
   __syncthreads();
   constexpr int NG = 256 / OBW, GR = TQ / NG;   // row groups for the coefficients
   const int ca = t % OBW, cg = t / OBW;       // coefficient a, row group cg
+  // thread t < OBW accumulates R[t][j] of the current column j
+  double racc = 0.0;
   auto colsq = [&](int j) {
     const double v = (t < TQ) ? T[t][j] : 0.0;
     return block_sum256(v * v, sh);
   };
-  // x <- x - sum_{a<j} coef_a q_a, coefficients accumulated into Rl[a][j] * w
+  // x <- x - sum_{a<j} coef_a q_a, coefficients accumulated into R[a][j] * w
+  // (four independent partial sums in the loops: the LDS loads of a loop
+  // are then issued back to back instead of one round trip per term)
   auto project = [&](int j, double w) {
     double pp = 0.0;
-    if (ca < j)
-      for (int rr = cg * GR; rr < cg * GR + GR; ++rr) pp += T[rr][ca] * T[rr][j];
+    if (ca < j) {
+      double p4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+      for (int rr = cg * GR; rr < cg * GR + GR; rr += 4)
+        for (int u = 0; u < 4; ++u) p4[u] += T[rr + u][ca] * T[rr + u][j];
+      pp = (p4[0] + p4[1]) + (p4[2] + p4[3]);
+    }
     red[cg][ca] = pp;
     __syncthreads();
     if (t < j) {
       double cs = 0.0;
       for (int g = 0; g < NG; ++g) cs += red[g][t];
       coef[t] = cs;
-      Rl[t][j] += w * cs;
+      racc += w * cs;
     }
     __syncthreads();
     if (t < TQ) {
-      double x = T[t][j];
-      for (int aa = 0; aa < j; ++aa) x -= coef[aa] * T[t][aa];
-      T[t][j] = x;
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      int aa = 0;
+      for (; aa + 4 <= j; aa += 4)
+        for (int u = 0; u < 4; ++u) s4[u] += coef[aa + u] * T[t][aa + u];
+      for (; aa < j; ++aa) s4[0] += coef[aa] * T[t][aa];
+      T[t][j] -= (s4[0] + s4[1]) + (s4[2] + s4[3]);
     }
     __syncthreads();
+  };
+  auto put_r = [&](int j, double rjj) {
+    if (r != nullptr && t < OBW)
+      r[((int64_t)blockIdx.x * OBW + t) * OBW + j] = t < j ? racc : (t == j ? rjj : 0.0);
+    racc = 0.0;
   };
   for (int j = 0; j < nb; ++j) {
     if (top && final && dead[c0 + j]) {
       if (t < TQ) T[t][j] = 0.0;
+      put_r(j, 0.0);
       __syncthreads();
       continue;
     }
@@ -483,53 +519,61 @@ __global__ __launch_bounds__(256) void tsqr_local_kernel(
       }
     }
     if (dep && t < TQ) T[t][j] = 0.0;
-    if (t == 0) {
-      Rl[j][j] = rjj;
-      if (top && !final) dead[c0 + j] = dep;
-    }
+    put_r(j, rjj);
+    if (t == 0 && top && !final) dead[c0 + j] = dep;
     __syncthreads();
   }
+  for (int j = nb; j < OBW; ++j) put_r(j, 0.0);
   for (int e = t; e < TQ * OBW; e += 256) {
     const int rr = e / OBW, cc = e % OBW;
     if (i0 + rr < rows && cc < qcols) q[(int64_t)(i0 + rr) * ldq + cc] = T[rr][cc];
   }
-  if (r != nullptr)
-    for (int e = t; e < OBW * OBW; e += 256) {
-      const int rr = e / OBW, cc = e % OBW;
-      r[((int64_t)blockIdx.x * OBW + rr) * OBW + cc] = Rl[rr][cc];
-    }
 }
 
 // dst rows of chunk b = Q rows of chunk b (TQ x OBW, ld OBW) times W rows
-// [OBW b, OBW b + OBW) (ld OBW); nb columns.
+// [OBW b, OBW b + OBW) (ld OBW); nb columns.  The chunk's rows go through
+// LDS in two halves.
 __global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restrict__ Q, int rows,
                                                          const double* __restrict__ W, int nb,
                                                          double* __restrict__ dst, int64_t ldd,
                                                          const int* __restrict__ healthy) {
+  constexpr int TH = TQ / 2;
   __shared__ double Ws[OBW][OBP];
-  __shared__ double Qs[TQ][OBP];
+  __shared__ double Qs[TH][OBP];
   if (*healthy) return;
   const int t = threadIdx.x;
-  const int i0 = blockIdx.x * TQ;
   for (int e = t; e < OBW * OBW; e += 256)
     Ws[e / OBW][e % OBW] = W[((int64_t)blockIdx.x * OBW + e / OBW) * OBW + e % OBW];
-  for (int e = t; e < TQ * OBW; e += 256) {
-    const int rr = e / OBW, cc = e % OBW;
-    Qs[rr][cc] = (i0 + rr < rows) ? Q[(int64_t)(i0 + rr) * OBW + cc] : 0.0;
-  }
-  __syncthreads();
-  for (int e = t; e < TQ * OBW; e += 256) {
-    const int rr = e / OBW, cc = e % OBW;
-    if (i0 + rr >= rows || cc >= nb) continue;
-    double v = 0.0;
-    for (int a2 = 0; a2 < OBW; ++a2) v += Qs[rr][a2] * Ws[a2][cc];
-    dst[(int64_t)(i0 + rr) * ldd + cc] = v;
+  for (int h = 0; h < 2; ++h) {
+    const int i0 = blockIdx.x * TQ + h * TH;
+    for (int e = t; e < TH * OBW; e += 256) {
+      const int rr = e / OBW, cc = e % OBW;
+      Qs[rr][cc] = (i0 + rr < rows) ? Q[(int64_t)(i0 + rr) * OBW + cc] : 0.0;
+    }
+    __syncthreads();
+    // thread: column cc = t % 64 of rows t / 64 + 4 q (independent sums)
+    const int cc = t & 63, r0 = t >> 6;
+    double acc[TH / 4];
+#pragma unroll
+    for (int q = 0; q < TH / 4; ++q) acc[q] = 0.0;
+    for (int a2 = 0; a2 < OBW; ++a2) {
+      const double wv = Ws[a2][cc];
+#pragma unroll
+      for (int q = 0; q < TH / 4; ++q) acc[q] += Qs[r0 + 4 * q][a2] * wv;
+    }
+    if (cc < nb)
+#pragma unroll
+      for (int q = 0; q < TH / 4; ++q) {
+        const int rr = r0 + 4 * q;
+        if (i0 + rr < rows) dst[(int64_t)(i0 + rr) * ldd + cc] = acc[q];
+      }
+    __syncthreads();
   }
 }
 
 // Cholesky path of the in-block step.  G (nb x nb) is the Gram matrix of the
-// block's columns after the projection of the earlier blocks.  One wavefront
-// factors G = R^T R and inverts R.  The block is "healthy" when the
+// block's columns after the projection of the earlier blocks.  One
+// workgroup factors G = R^T R and inverts R.  The block is "healthy" when the
 // condition number of the column-scaled block, estimated from R^{-1}, is at
 // most 1e6 on the first visit (Cholesky QR then leaves orthogonality errors
 // below ~1e-4, which the second visit removes) and at most twice its value
@@ -539,6 +583,10 @@ __global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restric
 // Gram-Schmidt fallback, which decides dependence), and on the first visit
 // no column is at or below 1e-13 of its original norm.  Exactly zero columns
 // are dead.  Ri = R^{-1} (dead rows and columns zero).
+//
+// Every thread derives the pivot of a step itself from LDS (no serial thread,
+// no extra barrier), so a step of the factorisation or of the inversion ends
+// with one barrier.
 __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restrict__ G, int nb,
                                                          int c0, const double* __restrict__ nrm0,
                                                          int* __restrict__ dead, int final,
@@ -548,57 +596,112 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restric
   __shared__ double R[OBW][OBP];
   __shared__ double X[OBW][OBP];    // R^{-1}
   __shared__ double gd[OBW];        // diagonal of G
-  __shared__ int ok, isdead[OBW];
+  __shared__ double sgd[OBW];       // its square roots
+  __shared__ double n0[OBW];        // original column norms
+  __shared__ int isdead[OBW];
+  __shared__ double part_s;
+  __shared__ int live_s, ok_s;
   const int t = threadIdx.x;
+  const int ti = t >> 4, tk = t & 15;   // 16 x 16 thread tile of the updates
   for (int e = t; e < OBW * OBW; e += 256) {
     const int i = e / OBW, j = e % OBW;
     W[i][j] = (i < nb && j < nb) ? G[i * nb + j] : 0.0;
     R[i][j] = 0.0;
     X[i][j] = (i == j && i < nb) ? 1.0 : 0.0;
   }
-  if (t < nb) gd[t] = G[t * nb + t];
-  if (t == 0) ok = 1;
+  if (t < OBW) {
+    gd[t] = t < nb ? G[t * nb + t] : 0.0;
+    sgd[t] = sqrt(gd[t]);
+    n0[t] = t < nb ? nrm0[c0 + t] : 0.0;
+  }
   __syncthreads();
+  const double delta = final ? 0.25 : 1e-12;
+  bool ok = true;
   // right-looking Cholesky: the pivot of step j is W[j][j] after the
-  // updates of steps < j; the trailing block is then updated in parallel
+  // updates of steps < j; row j of R and the trailing update of step j read
+  // only row j of W, which step j does not write
   for (int j = 0; j < nb; ++j) {
+    const double d = W[j][j], gjj = gd[j];
+    const bool dd = (gjj == 0.0);
+    if (!dd) {
+      if (!(d >= delta * gjj)) ok = false;
+      if (!final && !(sgd[j] > 1e-13 * n0[j])) ok = false;
+    }
+    const double rjj = (dd || !(d > 0.0)) ? 0.0 : sqrt(d);
+    const double inv = rjj > 0.0 ? 1.0 / rjj : 0.0;
     if (t == 0) {
-      const double d = W[j][j], gjj = gd[j];
-      int dd = 0;
-      if (gjj == 0.0) {
-        dd = 1;                       // exactly zero column
-      } else {
-        const double delta = final ? 0.25 : 1e-12;
-        if (!(d >= delta * gjj)) ok = 0;
-        if (!final && !(sqrt(gjj) > 1e-13 * nrm0[c0 + j])) ok = 0;
+      isdead[j] = dd ? 1 : 0;
+      R[j][j] = rjj;
+    }
+    if (t > j && t < nb) R[j][t] = W[j][t] * inv;
+    // this thread's (up to) 4 x 4 entries of the trailing block: all loads
+    // first, then all stores
+    {
+      double ri[4], rk[4], w[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int i = j + 1 + ti + 16 * a, k = j + 1 + tk + 16 * a;
+        ri[a] = i < nb ? W[j][i] * inv : 0.0;
+        rk[a] = k < nb ? W[j][k] * inv : 0.0;
       }
-      isdead[j] = dd;
-      R[j][j] = (dd || !(d > 0.0)) ? 0.0 : sqrt(d);
-    }
-    __syncthreads();
-    const double rjj = R[j][j];
-    if (t > j && t < nb) R[j][t] = rjj > 0.0 ? W[j][t] / rjj : 0.0;
-    __syncthreads();
-    const int w = nb - j - 1;
-    for (int e = t; e < w * w; e += 256) {
-      const int i = j + 1 + e / w, k = j + 1 + e % w;
-      W[i][k] -= R[j][i] * R[j][k];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = j + 1 + ti + 16 * a, k = j + 1 + tk + 16 * b;
+          w[a][b] = (i < nb && k < nb) ? W[i][k] : 0.0;
+        }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = j + 1 + ti + 16 * a, k = j + 1 + tk + 16 * b;
+          if (i < nb && k < nb) W[i][k] = w[a][b] - ri[a] * rk[b];
+        }
     }
     __syncthreads();
   }
-  // R^{-1} by backward elimination on X = I, one row of R at a time from the
-  // bottom (dead rows and columns stay zero)
-  for (int r = nb - 1; r >= 0; --r) {
+  // R^{-1} by backward elimination of [R | I] without row scaling: step r
+  // subtracts (R[i][r] / R[r][r]) times row r from the rows i < r (their R
+  // part is untouched by the earlier steps in column r, and row r itself is
+  // not written), then row r is divided by R[r][r] at the end.  Dead rows
+  // (R[r][r] = 0) take no part and come out zero.
+  for (int r = nb - 1; r > 0; --r) {
     const double rr = R[r][r];
-    if (t >= r && t < nb) X[r][t] = rr > 0.0 ? X[r][t] / rr : 0.0;
-    __syncthreads();
-    const int w = nb - r;
-    for (int e = t; e < r * w; e += 256) {
-      const int i = e / w, k = r + e % w;
-      X[i][k] -= R[i][r] * X[r][k];
+    if (rr > 0.0) {
+      const double inv = 1.0 / rr;
+      double f[4], xr[4], x[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int i = ti + 16 * a, k = r + tk + 16 * a;
+        f[a] = i < r ? R[i][r] * inv : 0.0;
+        xr[a] = k < nb ? X[r][k] : 0.0;
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = ti + 16 * a, k = r + tk + 16 * b;
+          x[a][b] = (i < r && k < nb) ? X[i][k] : 0.0;
+        }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int i = ti + 16 * a, k = r + tk + 16 * b;
+          if (i < r && k < nb) X[i][k] = x[a][b] - f[a] * xr[b];
+        }
     }
     __syncthreads();
   }
+  for (int e = t; e < nb * nb; e += 256) {
+    const int i = e / nb, k = e % nb;
+    const double rr = R[i][i];
+    X[i][k] = rr > 0.0 ? X[i][k] / rr : 0.0;
+  }
+  // every thread took the same decisions from the same LDS values
+  if (t == 0) ok_s = ok ? 1 : 0;
+  __syncthreads();
   // kappa_F = sqrt(live columns) * ||diag(sqrt(G_jj)) R^{-1}||_F bounds the
   // condition number of the column-scaled block (the columns of
   // R diag(1/sqrt(G_jj)) have unit norm), which sets the accuracy of
@@ -608,7 +711,7 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restric
     int live = 0;
     if (t < nb) {
       for (int r = 0; r <= t; ++r) {
-        const double x = sqrt(gd[r]) * X[r][t];
+        const double x = sgd[r] * X[r][t];
         part += x * x;
       }
       live = isdead[t] ? 0 : 1;
@@ -619,7 +722,7 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restric
     }
     const double kappa = sqrt((double)live * part);
     // an orthonormal block has kappa_F = live exactly
-    const int good = ok && (kappa <= (final ? 2.0 * (double)(live > 0 ? live : 1) : 1e6));
+    const int good = ok_s && (kappa <= (final ? 2.0 * (double)(live > 0 ? live : 1) : 1e6));
     if (t < nb) {
       for (int r = 0; r < nb; ++r) Ri[r * nb + t] = X[r][t];
       if (!final && good) dead[c0 + t] = isdead[t];
@@ -645,12 +748,22 @@ __global__ __launch_bounds__(256) void apply_ri_kernel(double* __restrict__ U, i
     P[r][cc] = (i0 + r < m) ? U[(int64_t)(i0 + r) * kk + c0 + cc] : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < 64 * nb; e += 256) {
-    const int r = e / nb, cc = e % nb;
-    if (i0 + r >= m) continue;
-    double v = 0.0;
-    for (int a = 0; a <= cc; ++a) v += P[r][a] * Rs[a][cc];
-    U[(int64_t)(i0 + r) * kk + c0 + cc] = v;
+  // thread: column cc = t % 64 of rows t / 64 + 4 q (16 independent sums;
+  // R^{-1} is upper triangular, so only a <= cc contributes)
+  const int cc = t & 63, r0 = t >> 6;
+  if (cc >= nb) return;
+  double acc[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+  for (int a = 0; a <= cc; ++a) {
+    const double rv = Rs[a][cc];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] += P[r0 + 4 * q][a] * rv;
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int r = r0 + 4 * q;
+    if (i0 + r < m) U[(int64_t)(i0 + r) * kk + c0 + cc] = acc[q];
   }
 }
 
@@ -890,14 +1003,17 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
     const double tol_in = std::min(32.0, 0.5 * std::max((double)r, 4.0)) * eps;
     const int inner_sweeps = 1;
     const int max_sweeps = 14;
+    // XCD of this SVD's Jacobi rounds (concurrent SVDs have their buffers
+    // megabytes apart, so they mostly land on different XCDs)
+    const int xslot = (int)(((uintptr_t)X >> 20) & 7);
     for (int sw = 0; sw < max_sweeps; ++sw) {
       for (int rd = 0; rd < nb - 1; ++rd) {
         // work of one round if every pair rotates: Gram + update of X and V
         // the work is data dependent: the kernel tallies it on the device
         ProfScope ps(c, K_SVD_ROUND, 0.0, 0.0);
-        hipLaunchKernelGGL(jac_round_kernel, dim3(nb / 2), dim3(256), 0, c.stream, X, r,
+        hipLaunchKernelGGL(jac_round_kernel, dim3(8 * (nb / 2)), dim3(256), 0, c.stream, X, r,
                            (int64_t)r, V, n, nb, rd, tol, tol_in, inner_sweeps, fro, flags,
-                           c.prof ? c.work : nullptr);
+                           c.prof ? c.work : nullptr, xslot);
       }
       hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(1), 0, c.stream, flags);
     }

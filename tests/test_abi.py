@@ -89,7 +89,8 @@ def test_null_solver_calls(lib):
                     (lib.ctm_energy, (None, None, None, None)),
                     (lib.ctm_get_env, (None, 0, None, 0, None, None)),
                     (lib.ctm_set_env, (None, 0, None, 1, 1)),
-                    (lib.ctm_set_precision, (None, 0)), (lib.ctm_profile, (None, 1)),
+                    (lib.ctm_set_precision, (None, 0)), (lib.ctm_set_graphs, (None, 1)),
+                    (lib.ctm_profile, (None, 1)),
                     (lib.ctm_profile_read, (None, 0, None, None, None, None))]:
         assert f(*args) == P.CTM_EINVAL
     assert lib.ctm_moves_done(None) == -1
