@@ -61,11 +61,33 @@ __device__ __forceinline__ void rr_pair(int nb, int round, int i, int* a, int* b
   *b = pos(nb - 1 - i);
 }
 
+// Reciprocal and reciprocal square root from the hardware estimates and two
+// Newton steps (each squares the relative error).  A dependent FP64
+// operation costs tens of cycles on this GPU, and the compiler's correctly
+// rounded division and square root are chains of about ten of them, which
+// set the pace of the serial steps below; these take five to seven and agree
+// with the rounded results to about an ulp.  Arguments are positive and
+// finite where they are used.
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = fma(y, fma(-x, y, 1.0), y);
+  y = fma(y, fma(-x, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+  return y;
+}
+
 // Rotation test for a column pair (see the file comment): thr = 4 eps ||M||_F.
+// Compared in squares (Gram entries of normalised data are far from overflow).
 __device__ __forceinline__ bool needs_rotation(double app, double aqq, double apq, double tol,
                                                double gnoise, double thr) {
-  return fmin(app, aqq) > gnoise && fabs(apq) > tol * sqrt(fabs(app * aqq)) &&
-         fabs(apq) > thr * sqrt(fmax(app, aqq));
+  const double a2 = apq * apq;
+  return fmin(app, aqq) > gnoise && a2 > tol * tol * fabs(app * aqq) &&
+         a2 > thr * thr * fmax(app, aqq);
 }
 
 // in-LDS cyclic Jacobi on the symmetric positive semi-definite 32 x 32 Gram
@@ -86,10 +108,19 @@ __device__ __forceinline__ bool jac_rotation(double app, double aqq, double apq,
   *s = 0.0;
   *tt = 0.0;
   if (!needs_rotation(app, aqq, apq, tol, gnoise, thr)) return false;
-  const double tau = (aqq - app) / (2.0 * apq);
-  *tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  *c = 1.0 / sqrt(1.0 + *tt * *tt);
-  *s = *tt * *c;
+  const double tau = (aqq - app) * rcp_nr(2.0 * apq);
+  const double at = fabs(tau);
+  double t;
+  if (at > 1e100) {   // sqrt(1 + tau^2) = |tau| to working precision
+    t = 0.5 * rcp_nr(at);
+  } else {
+    const double u = fma(tau, tau, 1.0);
+    t = rcp_nr(at + u * rsq_nr(u));
+  }
+  t = tau >= 0.0 ? t : -t;
+  *tt = t;
+  *c = rsq_nr(fma(t, t, 1.0));
+  *s = t * *c;
   return true;
 }
 
@@ -494,28 +525,31 @@ __global__ __launch_bounds__(256) void tsqr_local_kernel(
       __syncthreads();
       continue;
     }
-    const double x0 = sqrt(colsq(j));
+    // squared norms; r = q rsq(q) and 1 / r = rsq(q) where q > 0
+    const double q0 = colsq(j);
     project(j, 1.0);
     project(j, 1.0);
-    const double r1 = sqrt(colsq(j));
+    const double q1 = colsq(j);
+    const double i1 = q1 > 0.0 ? rsq_nr(q1) : 0.0, r1 = q1 * i1;
     if (t == 0) {
       bool d;
       if (top) d = final ? !(r1 > 0.5) : !(r1 > 1e-13 * nrm0[c0 + j]);
-      else d = !(r1 > 1e-13 * x0);
+      else d = !(q1 > 1e-26 * q0);
       dep = d ? 1 : 0;
     }
     __syncthreads();
     double rjj = 0.0;
     if (!dep) {
-      if (t < TQ) T[t][j] /= r1;
+      if (t < TQ) T[t][j] *= i1;
       __syncthreads();
       project(j, r1);
-      const double r2 = sqrt(colsq(j));
-      if (t == 0) dep = (r2 > 0.5) ? 0 : 1;
+      const double q2 = colsq(j);
+      if (t == 0) dep = (q2 > 0.25) ? 0 : 1;
       __syncthreads();
       if (!dep) {
-        if (t < TQ) T[t][j] /= r2;
-        rjj = r1 * r2;
+        const double i2 = rsq_nr(q2);
+        if (t < TQ) T[t][j] *= i2;
+        rjj = r1 * (q2 * i2);
       }
     }
     if (dep && t < TQ) T[t][j] = 0.0;
@@ -627,8 +661,9 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restric
       if (!(d >= delta * gjj)) ok = false;
       if (!final && !(sgd[j] > 1e-13 * n0[j])) ok = false;
     }
-    const double rjj = (dd || !(d > 0.0)) ? 0.0 : sqrt(d);
-    const double inv = rjj > 0.0 ? 1.0 / rjj : 0.0;
+    const bool piv = !dd && d > 0.0;
+    const double inv = piv ? rsq_nr(d) : 0.0;
+    const double rjj = piv ? d * inv : 0.0;
     if (t == 0) {
       isdead[j] = dd ? 1 : 0;
       R[j][j] = rjj;
@@ -669,7 +704,7 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restric
   for (int r = nb - 1; r > 0; --r) {
     const double rr = R[r][r];
     if (rr > 0.0) {
-      const double inv = 1.0 / rr;
+      const double inv = rcp_nr(rr);
       double f[4], xr[4], x[4][4];
 #pragma unroll
       for (int a = 0; a < 4; ++a) {
@@ -697,7 +732,7 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restric
   for (int e = t; e < nb * nb; e += 256) {
     const int i = e / nb, k = e % nb;
     const double rr = R[i][i];
-    X[i][k] = rr > 0.0 ? X[i][k] / rr : 0.0;
+    X[i][k] = rr > 0.0 ? X[i][k] * rcp_nr(rr) : 0.0;
   }
   // every thread took the same decisions from the same LDS values
   if (t == 0) ok_s = ok ? 1 : 0;
