@@ -618,6 +618,11 @@ __global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restric
 // no column is at or below 1e-13 of its original norm.  Exactly zero columns
 // are dead.  Ri = R^{-1} (dead rows and columns zero).
 //
+// With shift > 0 the factorisation is of G + shift diag(G) and the block is
+// taken as it comes (no condition test): Q = A R^{-1} then spans exactly the
+// columns of A (R is invertible on the live columns) and is orthonormal only
+// up to about shift kappa^2, which is all a power-iteration basis needs.
+//
 // Every thread derives the pivot of a step itself from LDS (no serial thread,
 // no extra barrier), so a step of the factorisation or of the inversion ends
 // with one barrier.
@@ -625,7 +630,7 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restric
                                                          int c0, const double* __restrict__ nrm0,
                                                          int* __restrict__ dead, int final,
                                                          double* __restrict__ Ri,
-                                                         int* __restrict__ healthy) {
+                                                         int* __restrict__ healthy, double shift) {
   __shared__ double W[OBW][OBP];    // G, overwritten by the trailing updates
   __shared__ double R[OBW][OBP];
   __shared__ double X[OBW][OBP];    // R^{-1}
@@ -639,7 +644,7 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restric
   const int ti = t >> 4, tk = t & 15;   // 16 x 16 thread tile of the updates
   for (int e = t; e < OBW * OBW; e += 256) {
     const int i = e / OBW, j = e % OBW;
-    W[i][j] = (i < nb && j < nb) ? G[i * nb + j] : 0.0;
+    W[i][j] = (i < nb && j < nb) ? G[i * nb + j] * (i == j ? 1.0 + shift : 1.0) : 0.0;
     R[i][j] = 0.0;
     X[i][j] = (i == j && i < nb) ? 1.0 : 0.0;
   }
@@ -757,7 +762,8 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restric
     }
     const double kappa = sqrt((double)live * part);
     // an orthonormal block has kappa_F = live exactly
-    const int good = ok_s && (kappa <= (final ? 2.0 * (double)(live > 0 ? live : 1) : 1e6));
+    const int good = shift > 0.0 ||
+                     (ok_s && (kappa <= (final ? 2.0 * (double)(live > 0 ? live : 1) : 1e6)));
     if (t < nb) {
       for (int r = 0; r < nb; ++r) Ri[r * nb + t] = X[r][t];
       if (!final && good) dead[c0 + t] = isdead[t];
@@ -913,10 +919,13 @@ void tsqr_fallback(Ctx& c, double* A, int m, int kk, int c0, int nbk, const doub
 }
 
 // Orthonormalise the kk columns of row-major A (m x kk) in place, in order,
-// by block classical Gram-Schmidt applied twice (BCGS2): for each block of 32
+// by block classical Gram-Schmidt applied twice (BCGS2): for each block of 64
 // columns, project out the earlier blocks (one GEMM pair), orthonormalise
 // inside the block (Cholesky QR when the block is well conditioned, else
-// classical Gram-Schmidt twice), and repeat both steps.
+// classical Gram-Schmidt twice), and repeat both steps.  With rounds = 1
+// (the bases between power steps of the range finder, which need a
+// normalised basis of the same span, not one orthonormal to working
+// accuracy) the first in-block step is a shifted Cholesky QR.
 // The second projection comes after the first in-block normalisation, so a
 // nearly dependent column, which shrinks to a small residual inside the
 // block, is still made orthogonal to the earlier blocks.  Columns dependent
@@ -924,6 +933,13 @@ void tsqr_fallback(Ctx& c, double* A, int m, int kk, int c0, int nbk, const doub
 // orthonormal and span the columns of A up to rounding.
 void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
   constexpr int OB = OBW;
+  // one round asked for (the bases between power steps): the block's first
+  // factorisation is a shifted Cholesky QR, which cannot fail and keeps the
+  // span, and the second a plain one under the first-visit test (orthogonal
+  // to ~1e-4 at worst), so the columns come out normalised without the
+  // Gram-Schmidt tree in most blocks
+  const bool loose = rounds == 1;
+  if (loose) rounds = 2;
   const size_t mk = c.arena.mark();
   const int rows = 64;
   const int chunks = (m + rows - 1) / rows;
@@ -954,13 +970,14 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
       gemm(c, F64, nbk, nbk, m, 1.0, A + c0, kk, 1, A + c0, kk, 0, 0.0, Gb, nbk);
       if (!c.dry) {
         ProfScope ps(c, K_SVD_OTHER, 2.0 * m * nbk * nbk, 8.0 * 2.0 * m * nbk);
+        const bool shifted = loose && pass == 0;
         hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(256), 0, c.stream, Gb, nbk, c0, nrm0,
-                           dead, pass, Ri, healthy);
+                           dead, loose ? 0 : pass, Ri, healthy, shifted ? 1e-12 : 0.0);
         hipLaunchKernelGGL(apply_ri_kernel, dim3((m + 63) / 64), dim3(256), 0, c.stream, A, m, kk,
                            c0, nbk, Ri, healthy);
         c.check_launch();
       }
-      tsqr_fallback(c, A, m, kk, c0, nbk, nrm0, dead, pass, healthy);
+      if (!(loose && pass == 0)) tsqr_fallback(c, A, m, kk, c0, nbk, nrm0, dead, loose ? 0 : pass, healthy);
     }
   }
   c.arena.release(mk);
