@@ -139,6 +139,12 @@ void scale_by_inv(Ctx& c, double* x, int64_t n, const double* nrm);
 void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U,
           double* S);
 
+// An orthonormal basis of the column space of the row-major m x n F64
+// matrix M (m >= n) at Q (m x n, row-major): the columns of M in order of
+// decreasing norm, orthonormalised; columns dependent on the earlier ones to
+// working precision come out zero.
+void range_basis(Ctx& c, const double* M, int m, int n, double* Q);
+
 // Normalised singular values of a p x q corner, zero padded to chi.
 void corner_spectrum(Ctx& c, const double* C, int p, int q, int chi, double* out);
 

@@ -281,6 +281,14 @@ Tensor anchor_standard(ctm_solver* s, Ctx& c, int r, int z, void* dst) {
 
 // Two-stage isometry of X[i,k,b,j] (bonded on (i,k,b)): v1 [i,k,mu], v2
 // [mu,b,nu], X''[nu,j] (Appendix, Fig. A(c)).  Outputs at the given buffers.
+//
+// The side isometries enter the move only through M' = C'1 T'2 C'2, where
+// the second-stage bond nu is summed over between X'' = v2^T X' and the v2
+// of the absorption chain: M' depends on v2 only through the projector
+// v2 v2^T.  When the second stage keeps every column (chi >= the columns of
+// X', cutoff at rounding level) that projector is the one onto the range of
+// X', so any orthonormal basis of the range serves: the norm-ordered QR
+// basis that the SVD would start from, without its Jacobi sweeps.
 void split_iso(ctm_solver* s, Ctx& c, const Tensor& X, void* d1, void* d2, void* dxx,
                Tensor* v1o, Tensor* v2o, Tensor* xxo) {
   const int64_t ni = X.dims[0], D = X.dims[1], nj = X.dims[3];
@@ -289,7 +297,14 @@ void split_iso(ctm_solver* s, Ctx& c, const Tensor& X, void* d1, void* d2, void*
   const int64_t c1 = v1.dims[1];
   v1 = reshape(v1, {ni, D, c1});
   Tensor Xp = contract(c, v1, "ikm", X, "iklj", "mlj", F64, F64);
-  Tensor v2 = isometry(s, c, Xp, c1 * D, nj, d2);
+  const bool full_range = s->chi >= nj && c1 * D >= nj && s->tau <= 1e-12;
+  Tensor v2;
+  if (full_range) {
+    range_basis(c, Xp.d(), (int)(c1 * D), (int)nj, (double*)d2);
+    v2 = make_view(d2, F64, {c1 * D, nj});
+  } else {
+    v2 = isometry(s, c, Xp, c1 * D, nj, d2);
+  }
   const int64_t c2 = v2.dims[1];
   v2 = reshape(v2, {c1, D, c2});
   Tensor Xpp = contract(c, v2, "mln", Xp, "mlj", "nj", F64, F64);

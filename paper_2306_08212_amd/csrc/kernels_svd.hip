@@ -1163,6 +1163,8 @@ void tsvd(Ctx& c, const double* M, int m, int n, int k, double tau, double* U, d
     tsvd_wide(c, M, m, n, k, tau, U, S);
 }
 
+void range_basis(Ctx& c, const double* M, int m, int n, double* Q) { orth_sorted(c, M, m, n, Q); }
+
 void corner_spectrum(Ctx& c, const double* C, int p, int q, int chi, double* out) {
   const int kk = std::min(chi, std::min(p, q));
   const size_t mk = c.arena.mark();
