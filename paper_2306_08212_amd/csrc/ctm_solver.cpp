@@ -409,9 +409,12 @@ void store_env(ctm_solver* s, int e, const Tensor& t) {
 
 // Insert one column into the left environment (frame r) and truncate.
 // Independent work runs as concurrent branches: the two anchors (standard
-// move) or the four side isometries and then the two split anchors (reduced
-// move), and finally the updates of the two rows x = a, b.
-void insert_column(ctm_solver* s, int r) {
+// move) or the side isometries and then the two split anchors (reduced
+// move), and finally the updates of the two rows x = a, b.  The right-side
+// isometries (from C2_z and T3_z, which a left move leaves unchanged) are
+// the same for both insertions of a move: they are kept in rside, computed
+// by the first reduced insertion (have_r false) and reused by the second.
+void insert_column(ctm_solver* s, int r, SideIso* rside, bool have_r) {
   Ctx& c = s->ctx;
   const int64_t D = s->D, cap = s->cap, chi = s->chi;
   const bool stdm = insertion_standard(s, r);
@@ -435,17 +438,19 @@ void insert_column(ctm_solver* s, int r) {
     }
   } else {
     SideIso side[2][2];   // [z][side]
-    for (int z = 0; z < 2; ++z)
-      for (int sd = 0; sd < 2; ++sd) {
-        side[z][sd].b1 = c.arena.alloc(sizeof(double) * cap * D * chi);
-        side[z][sd].b2 = c.arena.alloc(sizeof(double) * chi * D * chi);
-        side[z][sd].bc = c.arena.alloc(sizeof(double) * chi * cap);
-      }
+    for (int z = 0; z < 2; ++z) {
+      side[z][0].b1 = c.arena.alloc(sizeof(double) * cap * D * chi);
+      side[z][0].b2 = c.arena.alloc(sizeof(double) * chi * D * chi);
+      side[z][0].bc = c.arena.alloc(sizeof(double) * chi * cap);
+      side[z][1] = rside[z];
+    }
     std::vector<std::function<void(Ctx&)>> fs;
     for (int z = 0; z < 2; ++z)
       for (int sd = 0; sd < 2; ++sd)
-        fs.push_back([&, z, sd](Ctx& k) { side_iso(s, k, r, z, sd, &side[z][sd]); });
+        if (sd == 0 || !have_r)
+          fs.push_back([&, z, sd](Ctx& k) { side_iso(s, k, r, z, sd, &side[z][sd]); });
     run_branches(s, fs);
+    for (int z = 0; z < 2; ++z) rside[z] = side[z][1];
     void* d1[2];
     void* d2[2];
     for (int z = 0; z < 2; ++z) {
@@ -531,8 +536,22 @@ void do_move(ctm_solver* s, int r) {
   // random test matrices of the truncations depend only on their position in
   // the move, so a move from a given state is reproducible in any precision
   s->ctx.rng_calls = 0;
-  insert_column(s, r);
-  insert_column(s, r);
+  Ctx& c = s->ctx;
+  const int64_t D = s->D, cap = s->cap, chi = s->chi;
+  const size_t mk = c.arena.mark();
+  SideIso rside[2];
+  for (int z = 0; z < 2; ++z) {
+    rside[z].b1 = c.arena.alloc(sizeof(double) * cap * D * chi);
+    rside[z].b2 = c.arena.alloc(sizeof(double) * chi * D * chi);
+    rside[z].bc = c.arena.alloc(sizeof(double) * chi * cap);
+  }
+  bool have_r = false;
+  for (int k = 0; k < 2; ++k) {
+    const bool stdm = insertion_standard(s, r);
+    insert_column(s, r, rside, have_r);
+    have_r = have_r || !stdm;
+  }
+  c.arena.release(mk);
   s->moves++;
 }
 
