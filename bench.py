@@ -28,10 +28,17 @@ if ROOT not in sys.path:
 # lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s)
 PEAK = {"gemm_f64": (78.6e12, "TFLOP/s", "mfma"), "gemm_f32": (157.3e12, "TFLOP/s", "mfma"),
         "gemm_bf16": (2.5e15, "TFLOP/s", "mfma"), "permute": (8.0e12, "GB/s", "hbm"),
-        "svd_round": (78.6e12, "TFLOP/s", "alu")}
+        "svd_round": (78.6e12, "TFLOP/s", "alu"), "chol": (78.6e12, "TFLOP/s", "alu")}
 KERNEL_OF = {"gemm_f64": "gemm_f64_kernel", "gemm_f32": "gemm_f32_kernel",
              "gemm_bf16": "gemm_bf16_kernel", "permute": "permute_tile_kernel/permute_rows_kernel",
-             "svd_round": "jac_round_kernel"}
+             "svd_round": "jac_round_kernel", "chol": "chol_block_kernel"}
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
+# dispatch) at this workload, scaled by the readings for a plain 64 MiB copy
+# (FETCH_SIZE reads half of the bytes moved, WRITE_SIZE all of them):
+# profiles/hbm_counters_reduced_move_D8_chi256.md.  Only for kernels whose
+# code is the one the counters were taken on.
+TRAFFIC = {"chol_block_kernel": 1024.0 * (2.0 * 23.694 + 32.186),
+           "jac_round_kernel": 1024.0 * (2.0 * 297.143 + 173.725)}
 MOVE_ORDER = (0, 2, 1, 3)     # left, right, up, down
 
 
@@ -250,7 +257,8 @@ def main():
                    "d": d, "D": D, "chi": chi, "method": "reduced",
                    "precision": args.precision},
         "roofline": {"bound": bound, "kernel": KERNEL_OF[dom], "achieved": achieved,
-                     "peak": peak_u, "unit": unit, "frac": achieved / peak_u, "traffic": None,
+                     "peak": peak_u, "unit": unit, "frac": achieved / peak_u,
+                     "traffic": TRAFFIC.get(KERNEL_OF[dom]),
                      "launches_per_move": n / nprof, "avg_launch_us": 1e3 * kms / max(n, 1)},
         "move_model": {"flop_per_move": fm, "move_tflops": fm * moves_per_s / 1e12,
                        "frac_of_fp32_mfma_peak": fm * moves_per_s / 157.3e12,

@@ -149,7 +149,8 @@ int ctm_set_precision(ctm_solver *s, int precision);
  * the launches recorded, their summed duration in ms and their algorithmic
  * flop and byte counts (synchronises).  Classes: 0 FP64 GEMM kernel, 1 FP32
  * GEMM, 2 BF16 GEMM, 3 permute/cast, 4 Jacobi SVD round kernel, 5 other SVD
- * kernels, 6 norms, scaling and split-K sums, 7 device copies.  The work of
+ * kernels, 6 norms, scaling and split-K sums, 7 device copies, 8 the block
+ * Cholesky factorisation and inverse of the orthonormalisation.  The work of
  * a Jacobi round depends on the data (which column pairs still rotate), so
  * class 4's counts are tallied by the kernel itself on the device. */
 int ctm_profile(ctm_solver *s, int enable);

@@ -278,7 +278,7 @@ class Solver:
 
 
 KERNEL_CLASSES = ["gemm_f64", "gemm_f32", "gemm_bf16", "permute", "svd_round", "svd_other",
-                  "reduce", "copy"]
+                  "reduce", "copy", "chol"]
 
 ENV_NAMES = [f"{k}{i}{z}" for k in "CT" for i in range(1, 5) for z in "ab"]
 

@@ -54,7 +54,7 @@ struct Arena {
 // Kernel classes for live timing (HIP events around launches on the stream).
 enum KClass : int {
   K_GEMM_F64 = 0, K_GEMM_F32, K_GEMM_BF16, K_PERMUTE, K_SVD_ROUND, K_SVD_OTHER, K_REDUCE,
-  K_COPY, K_NCLASS
+  K_COPY, K_CHOL, K_NCLASS
 };
 
 struct Profiler {

@@ -969,10 +969,15 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
       // classical Gram-Schmidt twice otherwise (decided on the device)
       gemm(c, F64, nbk, nbk, m, 1.0, A + c0, kk, 1, A + c0, kk, 0, 0.0, Gb, nbk);
       if (!c.dry) {
-        ProfScope ps(c, K_SVD_OTHER, 2.0 * m * nbk * nbk, 8.0 * 2.0 * m * nbk);
         const bool shifted = loose && pass == 0;
-        hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(256), 0, c.stream, Gb, nbk, c0, nrm0,
-                           dead, loose ? 0 : pass, Ri, healthy, shifted ? 1e-12 : 0.0);
+        {
+          // Cholesky nb^3 / 3 and triangular inverse nb^3 / 3 flop; G in, R^{-1} out
+          const double b3 = (double)nbk * nbk * nbk;
+          ProfScope ps(c, K_CHOL, 2.0 * b3 / 3.0, 8.0 * 2.0 * nbk * nbk);
+          hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(256), 0, c.stream, Gb, nbk, c0, nrm0,
+                             dead, loose ? 0 : pass, Ri, healthy, shifted ? 1e-12 : 0.0);
+        }
+        ProfScope ps(c, K_SVD_OTHER, 2.0 * m * nbk * nbk, 8.0 * 2.0 * m * nbk);
         hipLaunchKernelGGL(apply_ri_kernel, dim3((m + 63) / 64), dim3(256), 0, c.stream, A, m, kk,
                            c0, nbk, Ri, healthy);
         c.check_launch();
