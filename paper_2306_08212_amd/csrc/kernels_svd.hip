@@ -623,129 +623,144 @@ __global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restric
 // columns of A (R is invertible on the live columns) and is orthonormal only
 // up to about shift kappa^2, which is all a power-iteration basis needs.
 //
-// Every thread derives the pivot of a step itself from LDS (no serial thread,
-// no extra barrier), so a step of the factorisation or of the inversion ends
-// with one barrier.
+// Layout for latency (every step of the factorisation is on the critical
+// path of the orthonormalisation): thread t keeps the 4 x 4 entries (t/16 +
+// 16 a, t%16 + 16 b) of the trailing matrix in registers for the whole
+// factorisation; a step reads the published pivot row from LDS, applies the
+// rank-1 update to its tile and the owners publish the next row, one barrier
+// per step.  The acceptance tests read the recorded pivots after the loop.
+// R^{-1} is formed by 16 x 16 blocks: the diagonal blocks by back
+// substitution, a column per thread, then the blocks above the diagonal by
+// block back substitution, three levels of small products.
 __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restrict__ G, int nb,
-                                                         int c0, const double* __restrict__ nrm0,
-                                                         int* __restrict__ dead, int final,
-                                                         double* __restrict__ Ri,
-                                                         int* __restrict__ healthy, double shift) {
-  __shared__ double W[OBW][OBP];    // G, overwritten by the trailing updates
-  __shared__ double R[OBW][OBP];
+                                                   int c0, const double* __restrict__ nrm0,
+                                                   int* __restrict__ dead, int final,
+                                                   double* __restrict__ Ri,
+                                                   int* __restrict__ healthy, double shift) {
+  __shared__ double Rw[OBW][OBP];   // row j of the trailing matrix as it stood at step j
   __shared__ double X[OBW][OBP];    // R^{-1}
-  __shared__ double gd[OBW];        // diagonal of G
-  __shared__ double sgd[OBW];       // its square roots
-  __shared__ double n0[OBW];        // original column norms
+  __shared__ double gd[OBW], sgd[OBW], n0[OBW], rinv[OBW];
   __shared__ int isdead[OBW];
-  __shared__ double part_s;
-  __shared__ int live_s, ok_s;
+  __shared__ int ok_s;
   const int t = threadIdx.x;
-  const int ti = t >> 4, tk = t & 15;   // 16 x 16 thread tile of the updates
-  for (int e = t; e < OBW * OBW; e += 256) {
-    const int i = e / OBW, j = e % OBW;
-    W[i][j] = (i < nb && j < nb) ? G[i * nb + j] * (i == j ? 1.0 + shift : 1.0) : 0.0;
-    R[i][j] = 0.0;
-    X[i][j] = (i == j && i < nb) ? 1.0 : 0.0;
-  }
+  const int ti = t >> 4, tk = t & 15;   // tile: rows ti + 16 a, columns tk + 16 b
+  double w[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int i = ti + 16 * a, k = tk + 16 * b;
+      w[a][b] = (i < nb && k < nb) ? G[i * nb + k] * (i == k ? 1.0 + shift : 1.0) : 0.0;
+    }
+  for (int e = t; e < OBW * OBW; e += 256) Rw[e >> 6][e & 63] = 0.0;
   if (t < OBW) {
     gd[t] = t < nb ? G[t * nb + t] : 0.0;
     sgd[t] = sqrt(gd[t]);
     n0[t] = t < nb ? nrm0[c0 + t] : 0.0;
+    rinv[t] = 0.0;
   }
   __syncthreads();
-  const double delta = final ? 0.25 : 1e-12;
-  bool ok = true;
-  // right-looking Cholesky: the pivot of step j is W[j][j] after the
-  // updates of steps < j; row j of R and the trailing update of step j read
-  // only row j of W, which step j does not write
+  if (ti == 0)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) Rw[0][tk + 16 * b] = w[0][b];
+  __syncthreads();
+  // the pivots are recorded and the acceptance tests run after the loop, so
+  // a step is the pivot's rsqrt, the rank-1 update of the thread's tile and
+  // the publication of the next row
+  __shared__ double pd[OBW];
   for (int j = 0; j < nb; ++j) {
-    const double d = W[j][j], gjj = gd[j];
-    const bool dd = (gjj == 0.0);
-    if (!dd) {
-      if (!(d >= delta * gjj)) ok = false;
-      if (!final && !(sgd[j] > 1e-13 * n0[j])) ok = false;
-    }
-    const bool piv = !dd && d > 0.0;
-    const double inv = piv ? rsq_nr(d) : 0.0;
-    const double rjj = piv ? d * inv : 0.0;
+    const double d = Rw[j][j];
+    const double inv = (d > 0.0 && gd[j] != 0.0) ? rsq_nr(d) : 0.0;
     if (t == 0) {
-      isdead[j] = dd ? 1 : 0;
-      R[j][j] = rjj;
+      rinv[j] = inv;
+      pd[j] = d;
     }
-    if (t > j && t < nb) R[j][t] = W[j][t] * inv;
-    // this thread's (up to) 4 x 4 entries of the trailing block: all loads
-    // first, then all stores
-    {
-      double ri[4], rk[4], w[4][4];
+    // row j of the factor, masked to the trailing columns by a multiply (the
+    // loads are unconditional: every entry of Rw is finite)
+    double ri[4], rk[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int i = j + 1 + ti + 16 * a, k = j + 1 + tk + 16 * a;
-        ri[a] = i < nb ? W[j][i] * inv : 0.0;
-        rk[a] = k < nb ? W[j][k] * inv : 0.0;
+    for (int a = 0; a < 4; ++a) {
+      const int i = ti + 16 * a, k = tk + 16 * a;
+      ri[a] = Rw[j][i] * (i > j ? inv : 0.0);
+      rk[a] = Rw[j][k] * (k > j ? inv : 0.0);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) w[a][b] = fma(-ri[a], rk[b], w[a][b]);
+    // the owners of row j + 1 publish it for the next step
+    const int jn = j + 1, an = jn >> 4;
+    if (jn < nb && ti == (jn & 15))
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const double v = an == 0 ? w[0][b] : (an == 1 ? w[1][b] : (an == 2 ? w[2][b] : w[3][b]));
+        Rw[jn][tk + 16 * b] = v;
       }
+    __syncthreads();
+  }
+  // acceptance: every nonzero column keeps a pivot d_j >= delta G_jj and, on
+  // the first visit, no column is at or below 1e-13 of its original norm;
+  // exactly zero columns are dead (wave 0 holds the columns)
+  bool ok = true;
+  if (t < 64) {
+    const double delta = final ? 0.25 : 1e-12;
+    bool good_j = true;
+    if (t < nb) {
+      const bool dd = gd[t] == 0.0;
+      isdead[t] = dd ? 1 : 0;
+      if (!dd) good_j = (pd[t] >= delta * gd[t]) && (final || sgd[t] > 1e-13 * n0[t]);
+    }
+    ok = __all(good_j);
+  }
+  // R in full: R[r][k] = Rw[r][k] rinv[r] (k > r), R[r][r] = sqrt(d_r), zero
+  // below; then R^{-1} by blocks of 16: the four diagonal blocks inverted at
+  // once (a column per thread, back substitution), then the blocks above the
+  // diagonal by block back substitution, X_ij = -X_ii sum_{i<k<=j} R_ik X_kj,
+  // one diagonal distance j - i at a time
+  for (int e = t; e < OBW * OBW; e += 256) {
+    const int r = e >> 6, k = e & 63;
+    const double ir = rinv[r];
+    Rw[r][k] = k > r ? Rw[r][k] * ir : (k == r && ir > 0.0 ? 1.0 / ir : 0.0);
+    X[r][k] = 0.0;
+  }
+  __syncthreads();
+  if (t < OBW) {
+    const int b0 = t & ~15, c = t & 15;   // block origin, column in the block
+    for (int r = c; r >= 0; --r) {
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k = r + 1; k <= c; ++k) s4[k & 3] += Rw[b0 + r][b0 + k] * X[b0 + k][b0 + c];
+      const double ir = rinv[b0 + r];
+      X[b0 + r][b0 + c] = ((r == c ? 1.0 : 0.0) - ((s4[0] + s4[1]) + (s4[2] + s4[3]))) * ir;
+    }
+  }
+  __syncthreads();
+  __shared__ double Tb[3][16][17];
+  for (int dist = 1; dist < 4; ++dist) {
+    const int nblk = 4 - dist;   // blocks (i, i + dist), i < nblk
+    // T_i = sum_{k = i+1}^{i+dist} R_{i k} X_{k, i+dist}
+    for (int e = t; e < nblk * 256; e += 256) {
+      const int bi = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
+      const int bj = bi + dist;
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int bk = bi + 1; bk <= bj; ++bk)
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+        for (int q = 0; q < 16; ++q) s4[q & 3] += Rw[16 * bi + rr][16 * bk + q] * X[16 * bk + q][16 * bj + cc];
+      Tb[bi][rr][cc] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    }
+    __syncthreads();
+    // X_{i, i+dist} = -X_ii T_i
+    for (int e = t; e < nblk * 256; e += 256) {
+      const int bi = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
+      const int bj = bi + dist;
+      double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int i = j + 1 + ti + 16 * a, k = j + 1 + tk + 16 * b;
-          w[a][b] = (i < nb && k < nb) ? W[i][k] : 0.0;
-        }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int i = j + 1 + ti + 16 * a, k = j + 1 + tk + 16 * b;
-          if (i < nb && k < nb) W[i][k] = w[a][b] - ri[a] * rk[b];
-        }
+      for (int q = 0; q < 16; ++q) s4[q & 3] += X[16 * bi + rr][16 * bi + q] * Tb[bi][q][cc];
+      X[16 * bi + rr][16 * bj + cc] = -((s4[0] + s4[1]) + (s4[2] + s4[3]));
     }
     __syncthreads();
   }
-  // R^{-1} by backward elimination of [R | I] without row scaling: step r
-  // subtracts (R[i][r] / R[r][r]) times row r from the rows i < r (their R
-  // part is untouched by the earlier steps in column r, and row r itself is
-  // not written), then row r is divided by R[r][r] at the end.  Dead rows
-  // (R[r][r] = 0) take no part and come out zero.
-  for (int r = nb - 1; r > 0; --r) {
-    const double rr = R[r][r];
-    if (rr > 0.0) {
-      const double inv = rcp_nr(rr);
-      double f[4], xr[4], x[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int i = ti + 16 * a, k = r + tk + 16 * a;
-        f[a] = i < r ? R[i][r] * inv : 0.0;
-        xr[a] = k < nb ? X[r][k] : 0.0;
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int i = ti + 16 * a, k = r + tk + 16 * b;
-          x[a][b] = (i < r && k < nb) ? X[i][k] : 0.0;
-        }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int i = ti + 16 * a, k = r + tk + 16 * b;
-          if (i < r && k < nb) X[i][k] = x[a][b] - f[a] * xr[b];
-        }
-    }
-    __syncthreads();
-  }
-  for (int e = t; e < nb * nb; e += 256) {
-    const int i = e / nb, k = e % nb;
-    const double rr = R[i][i];
-    X[i][k] = rr > 0.0 ? X[i][k] * rcp_nr(rr) : 0.0;
-  }
-  // every thread took the same decisions from the same LDS values
   if (t == 0) ok_s = ok ? 1 : 0;
   __syncthreads();
-  // kappa_F = sqrt(live columns) * ||diag(sqrt(G_jj)) R^{-1}||_F bounds the
-  // condition number of the column-scaled block (the columns of
-  // R diag(1/sqrt(G_jj)) have unit norm), which sets the accuracy of
-  // Cholesky QR (orthogonality ~ eps kappa^2).  Wave 0 holds the columns.
   if (t < 64) {
     double part = 0.0;
     int live = 0;
@@ -761,7 +776,6 @@ __global__ __launch_bounds__(256) void chol_block_kernel(const double* __restric
       live += __shfl_xor(live, off);
     }
     const double kappa = sqrt((double)live * part);
-    // an orthonormal block has kappa_F = live exactly
     const int good = shift > 0.0 ||
                      (ok_s && (kappa <= (final ? 2.0 * (double)(live > 0 ? live : 1) : 1e6)));
     if (t < nb) {
