@@ -37,8 +37,8 @@ KERNEL_OF = {"gemm_f64": "gemm_f64_kernel", "gemm_f32": "gemm_f32_kernel",
 # (FETCH_SIZE reads half of the bytes moved, WRITE_SIZE all of them):
 # profiles/hbm_counters_reduced_move_D8_chi256.md.  Only for kernels whose
 # code is the one the counters were taken on.
-TRAFFIC = {"chol_block_kernel": 1024.0 * (2.0 * 23.694 + 32.186),
-           "jac_round_kernel": 1024.0 * (2.0 * 297.143 + 173.725)}
+TRAFFIC = {"chol_block_kernel": 1024.0 * (2.0 * 28.019 + 32.186),
+           "jac_round_kernel": 1024.0 * (2.0 * 306.009 + 174.886)}
 MOVE_ORDER = (0, 2, 1, 3)     # left, right, up, down
 
 

@@ -101,27 +101,25 @@ __device__ __forceinline__ bool needs_rotation(double app, double aqq, double ap
 // it computes both rotations it needs from the pivot entries itself, so a
 // step is one read phase and one write phase (rows first, then columns, the
 // same order of operations as a row pass followed by a column pass).
+// Computed without branches (the pairs of a step diverge in whether they
+// rotate): every quantity is formed and the identity selected where the
+// pair needs no rotation.
 __device__ __forceinline__ bool jac_rotation(double app, double aqq, double apq, double tol,
                                              double gnoise, double thr, double* c, double* s,
                                              double* tt) {
-  *c = 1.0;
-  *s = 0.0;
-  *tt = 0.0;
-  if (!needs_rotation(app, aqq, apq, tol, gnoise, thr)) return false;
-  const double tau = (aqq - app) * rcp_nr(2.0 * apq);
+  const bool rot = needs_rotation(app, aqq, apq, tol, gnoise, thr);
+  const double tau = (aqq - app) * rcp_nr(2.0 * (rot ? apq : 1.0));
   const double at = fabs(tau);
-  double t;
-  if (at > 1e100) {   // sqrt(1 + tau^2) = |tau| to working precision
-    t = 0.5 * rcp_nr(at);
-  } else {
-    const double u = fma(tau, tau, 1.0);
-    t = rcp_nr(at + u * rsq_nr(u));
-  }
+  // sqrt(1 + tau^2) = |tau| to working precision beyond 1e100
+  const bool big = at > 1e100;
+  const double u = fma(big ? 0.0 : tau, big ? 0.0 : tau, 1.0);
+  double t = rcp_nr(big ? 2.0 * at : at + u * rsq_nr(u));
   t = tau >= 0.0 ? t : -t;
-  *tt = t;
-  *c = rsq_nr(fma(t, t, 1.0));
-  *s = t * *c;
-  return true;
+  const double cc = rsq_nr(fma(t, t, 1.0));
+  *tt = rot ? t : 0.0;
+  *c = rot ? cc : 1.0;
+  *s = rot ? t * cc : 0.0;
+  return rot;
 }
 
 __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double tol,
