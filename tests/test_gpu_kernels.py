@@ -63,7 +63,9 @@ def test_gemm_beta_accumulates():
                                          ((2, 8, 8, 8, 8), (0, 2, 1, 4, 3)),
                                          ((33, 2, 40, 9), (3, 1, 0, 2)),
                                          ((4, 5, 6, 7, 8, 3), (5, 4, 3, 2, 1, 0)),
-                                         ((100, 1, 37), (2, 1, 0)), ((1000,), (0,))])
+                                         ((100, 1, 37), (2, 1, 0)), ((1000,), (0,)),
+                                         ((70, 3, 130), (2, 1, 0)),
+                                         ((3, 96, 2, 130), (0, 3, 2, 1))])
 def test_permute_and_cast(shape, perm):
     log("permute", shape, perm)
     t = torch()
