@@ -342,3 +342,55 @@ def test_reduced_approaches_standard_as_chi_grows(D, chis):
         er = O.solve(A, B, chi, O.REDUCED, max_iters=30, tol=1e-10)["e_site"]
         gaps.append(abs(es - er))
     assert gaps[1] < gaps[0] / 10
+
+
+def test_side_second_stage_enters_only_through_its_range():
+    """The side isometries' second stage v_l^2 (and v_r^2) is summed over
+    between C'^1 = v_l^2T L' and the v_l^2 of the absorption chain, so M'
+    depends on it only through v_l^2 v_l^2T (Appendix, Sec. IV).  When that
+    stage keeps every column, any orthonormal basis of range(L') gives the
+    same M'; the GPU path takes the QR basis there.  A basis of a smaller
+    subspace changes M' (the check is sensitive)."""
+    A, B = site_tensors(2, 2, 11)
+    env = O.solve(A, B, 8, O.REDUCED, max_iters=3)["env"]
+    sites = {"a": A, "b": B}
+    for z in "ab":
+        _, _, parts = OC.anchor_reduced(env, sites, z, 8, return_parts=True)
+        vl1, vr1, vl2, vr2 = parts["vl1"], parts["vr1"], parts["vl2"], parts["vr2"]
+        Lp = np.einsum("ikm,iklj->mlj", vl1, parts["L"])
+        Rp = np.einsum("ikm,iklj->mlj", vr1, parts["R"])
+        c1, D, nj = Lp.shape
+        assert vl2.shape[2] == nj and vr2.shape[2] == Rp.shape[2]   # every column kept
+
+        def mprime(wl2, wr2):
+            Cp1 = np.einsum("mln,mlj->nj", wl2, Lp)
+            Cp2 = np.einsum("mln,mlj->nj", wr2, Rp)
+            Tp2 = OC.absorb_chain(env[f"T2{z}"], OC._site_in_T2(sites[z]), vl1, wl2, vr1, wr2)
+            Mp = np.einsum("nj,ndDo->jdDo", Cp1, Tp2)
+            return np.einsum("jdDo,ok->jdDk", Mp, Cp2)
+
+        ref = mprime(vl2, vr2)
+        np.testing.assert_allclose(ref, parts["Mp"], rtol=0, atol=1e-13 * np.abs(ref).max())
+        ql = np.linalg.qr(Lp.reshape(c1 * D, nj))[0].reshape(c1, D, nj)
+        qr = np.linalg.qr(Rp.reshape(Rp.shape[0] * D, -1))[0].reshape(Rp.shape[0], D, -1)
+        np.testing.assert_allclose(mprime(ql, qr), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+        rot = random_orthogonal(nj, 5)
+        rl = np.einsum("mln,nk->mlk", vl2, rot)
+        np.testing.assert_allclose(mprime(rl, vr2), ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+        assert np.abs(mprime(vl2[:, :, :-1], vr2) - ref).max() > 1e-6 * np.abs(ref).max()
+
+
+def test_left_move_changes_only_the_left_column():
+    """A left move (two insertions) rewrites C1, T1 and C4 of both
+    sublattices and nothing else (Sec. II), so the right-side isometries
+    built from C2 and T3 are the same for both insertions of a move; the GPU
+    path computes them once per move."""
+    A, B = site_tensors(2, 2, 12)
+    env = O.solve(A, B, 8, O.REDUCED, max_iters=2)["env"]
+    for r in range(4):
+        new = OC.move(env, A, B, r, 8, O.REDUCED)
+        changed = {k for k in O.ENV_KEYS if not np.array_equal(new[k], env[k])}
+        left = {f"{kind}{(i - 1 + r) % 4 + 1}{z}" for kind, i in (("C", 1), ("T", 1), ("C", 4))
+                for z in "ab"}
+        assert changed <= left and changed, (r, sorted(changed))
+        env = new
