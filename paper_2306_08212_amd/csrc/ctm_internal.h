@@ -62,6 +62,7 @@ struct Profiler {
     int cls;
     double flops, bytes;
     hipEvent_t e0, e1;
+    int launches;
   };
   std::vector<Rec> recs;
   long long n[K_NCLASS] = {0};
@@ -88,13 +89,16 @@ struct Ctx {
   Tensor alloc(int dt, const std::vector<int64_t>& dims);
 };
 
-// Records one launch (or a short sequence) of class cls when profiling is on.
+// Records one launch (or a short sequence counted as `launches` launches of
+// class cls) when profiling is on.
 struct ProfScope {
   Ctx& c;
   int cls;
   double flops, bytes;
+  int launches;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  ProfScope(Ctx& cx, int k, double f, double b) : c(cx), cls(k), flops(f), bytes(b) {
+  ProfScope(Ctx& cx, int k, double f, double b, int nl = 1)
+      : c(cx), cls(k), flops(f), bytes(b), launches(nl) {
     if (c.prof && !c.dry) {
       c.check(hipEventCreate(&e0));
       c.check(hipEventCreate(&e1));
@@ -104,7 +108,7 @@ struct ProfScope {
   ~ProfScope() {
     if (c.prof && !c.dry && e0) {
       c.check(hipEventRecord(e1, c.stream));
-      c.prof->recs.push_back({cls, flops, bytes, e0, e1});
+      c.prof->recs.push_back({cls, flops, bytes, e0, e1, launches});
     }
   }
 };

@@ -1076,13 +1076,15 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
     // megabytes apart, so they mostly land on different XCDs)
     const int xslot = (int)(((uintptr_t)X >> 20) & 7);
     for (int sw = 0; sw < max_sweeps; ++sw) {
-      for (int rd = 0; rd < nb - 1; ++rd) {
-        // work of one round if every pair rotates: Gram + update of X and V
-        // the work is data dependent: the kernel tallies it on the device
-        ProfScope ps(c, K_SVD_ROUND, 0.0, 0.0);
-        hipLaunchKernelGGL(jac_round_kernel, dim3(8 * (nb / 2)), dim3(256), 0, c.stream, X, r,
-                           (int64_t)r, V, n, nb, rd, tol, tol_in, inner_sweeps, fro, flags,
-                           c.prof ? c.work : nullptr, xslot);
+      {
+        // the rounds of a sweep are timed as one span (events around every
+        // launch would add each launch's dispatch to its duration); the
+        // work is data dependent: the kernel tallies it on the device
+        ProfScope ps(c, K_SVD_ROUND, 0.0, 0.0, nb - 1);
+        for (int rd = 0; rd < nb - 1; ++rd)
+          hipLaunchKernelGGL(jac_round_kernel, dim3(8 * (nb / 2)), dim3(256), 0, c.stream, X, r,
+                             (int64_t)r, V, n, nb, rd, tol, tol_in, inner_sweeps, fro, flags,
+                             c.prof ? c.work : nullptr, xslot);
       }
       hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(1), 0, c.stream, flags);
     }

@@ -258,7 +258,7 @@ void Profiler::collect() {
   for (Rec& r : recs) {
     float ms_ = 0.0f;
     if (hipEventElapsedTime(&ms_, r.e0, r.e1) == hipSuccess) {
-      n[r.cls] += 1;
+      n[r.cls] += r.launches;
       ms[r.cls] += ms_;
       flops[r.cls] += r.flops;
       bytes[r.cls] += r.bytes;
