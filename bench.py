@@ -30,7 +30,7 @@ PEAK = {"gemm_f64": (78.6e12, "TFLOP/s", "mfma"), "gemm_f32": (157.3e12, "TFLOP/
         "gemm_bf16": (2.5e15, "TFLOP/s", "mfma"), "permute": (8.0e12, "GB/s", "hbm"),
         "svd_round": (78.6e12, "TFLOP/s", "alu"), "chol": (78.6e12, "TFLOP/s", "alu")}
 KERNEL_OF = {"gemm_f64": "gemm_f64_kernel", "gemm_f32": "gemm_f32_kernel",
-             "gemm_bf16": "gemm_bf16_kernel", "permute": "permute_tile_kernel/permute_rows_kernel",
+             "gemm_bf16": "gemm_bf16_kernel", "permute": "permute_ctile_kernel/permute_rows_kernel",
              "svd_round": "jac_round_kernel", "chol": "chol_block_kernel"}
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
 # dispatch) at this workload, scaled by the readings for a plain 64 MiB copy
@@ -219,6 +219,21 @@ def main():
     breakdown = {k: {"launches": v[0] / nprof, "ms_per_move": v[1] / nprof,
                      "share": v[1] / ms_prof if ms_prof > 0 else 0.0}
                  for k, v in prof.items() if v[0]}
+    # achieved rates of the classes with an algorithmic count: matrix-core
+    # GEMMs in TFLOP/s (fraction of their dtype's dense peak), memory-bound
+    # classes in GB/s (fraction of 8 TB/s)
+    for k, rec in breakdown.items():
+        n_, kms, kfl, kby = prof[k]
+        if kms <= 0:
+            continue
+        if k.startswith("gemm") and kfl > 0:
+            tf = kfl / (kms / 1e3) / 1e12
+            rec["tflops"] = tf
+            rec["frac_of_peak"] = tf / (PEAK[k][0] / 1e12)
+        elif k in ("permute", "copy", "reduce") and kby > 0:
+            gbs = kby / (kms / 1e3) / 1e9
+            rec["gb_per_s"] = gbs
+            rec["frac_of_peak"] = gbs / 8000.0
     gemm_flops = sum(prof[k][2] for k in ("gemm_f64", "gemm_f32", "gemm_bf16")) / nprof
 
     fp64_mps = None

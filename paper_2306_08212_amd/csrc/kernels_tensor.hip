@@ -2,10 +2,11 @@
 //
 // The permute regroups tensor legs between the contractions of the move so
 // that contracted legs are contiguous for the GEMM.  When the innermost leg
-// survives it is a streaming copy; otherwise a 32 x 32 LDS tile transposes the
-// input-innermost and output-innermost legs so that both the reads and the
-// writes are coalesced.  All reductions are two-pass with a fixed block
-// count and a fixed summation order, so results are bitwise reproducible.
+// survives it is a streaming copy; otherwise a 64 x 64 LDS tile transposes the
+// run of trailing input legs against the run of output-innermost legs, so
+// that both the reads and the writes are coalesced 64-element rows.  All
+// reductions are two-pass with a fixed block count and a fixed summation
+// order, so results are bitwise reproducible.
 #include <cmath>
 
 #include <cstdio>
@@ -60,38 +61,75 @@ __global__ __launch_bounds__(256) void permute_rows_kernel(const Ti* __restrict_
   }
 }
 
-// general case: tile over (input innermost dim ia, output innermost dim ib)
+// Composite tiles: A is the run of trailing input dims (contiguous in the
+// input, so its linear index is its input offset) and B the run of dims that
+// are innermost in the output (contiguous there, so its linear index is its
+// output offset).  A 64 x 64 tile over (A, B) reads 64 contiguous input
+// elements and writes 64 contiguous output elements per row even when the
+// individual innermost dims are short (bond dimension D), which a tile over
+// single dims cannot.  The other offset of each side comes from decomposing
+// the composite index once per workgroup.
+struct PermTile {
+  int na, nb, nr;
+  int64_t A, B;
+  int64_t adim[kMaxDims], aout[kMaxDims];   // A dims, innermost first; output strides
+  int64_t bdim[kMaxDims], bin[kMaxDims];    // B dims, output-innermost first; input strides
+  int64_t rdim[kMaxDims], rin[kMaxDims], rout[kMaxDims];   // the other dims, outermost first
+};
+
 template <typename Ti, typename To>
-__global__ __launch_bounds__(256) void permute_tile_kernel(const Ti* __restrict__ in,
-                                                            To* __restrict__ out, PermArgs a,
-                                                            int ia, int ib, int64_t ntA,
-                                                            int64_t ntB, double scale) {
-  __shared__ double tile[32][33];
+__global__ __launch_bounds__(256) void permute_ctile_kernel(const Ti* __restrict__ in,
+                                                             To* __restrict__ out, PermTile p,
+                                                             int64_t ntA, int64_t ntB,
+                                                             double scale) {
+  __shared__ double tile[64][65];
+  __shared__ int64_t aoff_out[64], boff_in[64];
   int64_t bid = blockIdx.x;
   const int64_t tA = bid % ntA;
   bid /= ntA;
   const int64_t tB = bid % ntB;
   int64_t rest = bid / ntB;
   int64_t bi = 0, bo = 0;
-  for (int d = a.nd - 1; d >= 0; --d) {
-    if (d == ia || d == ib) continue;
-    const int64_t cd = rest % a.dims[d];
-    rest /= a.dims[d];
-    bi += cd * a.sin[d];
-    bo += cd * a.sout[d];
+  for (int d = p.nr - 1; d >= 0; --d) {
+    const int64_t cd = rest % p.rdim[d];
+    rest /= p.rdim[d];
+    bi += cd * p.rin[d];
+    bo += cd * p.rout[d];
   }
-  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
-  const int64_t NA = a.dims[ia], NB = a.dims[ib];
-  for (int j = ty; j < 32; j += 8) {
-    const int64_t xa = tA * 32 + tx, xb = tB * 32 + j;
+  const int t = threadIdx.x;
+  if (t < 64) {
+    int64_t x = tA * 64 + t, o = 0;
+    for (int k = 0; k < p.na; ++k) {
+      const int64_t q = x / p.adim[k];
+      o += (x - q * p.adim[k]) * p.aout[k];
+      x = q;
+    }
+    aoff_out[t] = o;
+  } else if (t < 128) {
+    int64_t x = tB * 64 + (t - 64), o = 0;
+    for (int k = 0; k < p.nb; ++k) {
+      const int64_t q = x / p.bdim[k];
+      o += (x - q * p.bdim[k]) * p.bin[k];
+      x = q;
+    }
+    boff_in[t - 64] = o;
+  }
+  __syncthreads();
+  const int tx = t & 63, ty = t >> 6;
+  const int64_t xa = tA * 64 + tx;
+#pragma unroll 4
+  for (int j = ty; j < 64; j += 4) {
+    const int64_t xb = tB * 64 + j;
     double v = 0.0;
-    if (xa < NA && xb < NB) v = ld(in, bi + xa * a.sin[ia] + xb * a.sin[ib]);
+    if (xa < p.A && xb < p.B) v = ld(in, bi + xa + boff_in[j]);
     tile[j][tx] = v;
   }
   __syncthreads();
-  for (int j = ty; j < 32; j += 8) {
-    const int64_t xb = tB * 32 + tx, xa = tA * 32 + j;
-    if (xa < NA && xb < NB) st(out, bo + xa * a.sout[ia] + xb * a.sout[ib], tile[tx][j] * scale);
+  const int64_t yb = tB * 64 + tx;
+#pragma unroll 4
+  for (int j = ty; j < 64; j += 4) {
+    const int64_t ya = tA * 64 + j;
+    if (ya < p.A && yb < p.B) st(out, bo + aoff_out[j] + yb, tile[tx][j] * scale);
   }
 }
 
@@ -111,11 +149,46 @@ void launch_permute(Ctx& c, const void* in, void* out, const PermArgs& a, double
     hipLaunchKernelGGL((permute_rows_kernel<Ti, To>), dim3((unsigned)blocks), dim3(256), 0,
                        c.stream, (const Ti*)in, (To*)out, a, total, scale);
   } else {
-    const int64_t ntA = (a.dims[ia] + 31) / 32, ntB = (a.dims[ib] + 31) / 32;
-    const int64_t rest = total / (a.dims[ia] * a.dims[ib]);
-    const int64_t blocks = ntA * ntB * rest;
-    hipLaunchKernelGGL((permute_tile_kernel<Ti, To>), dim3((unsigned)blocks), dim3(256), 0,
-                       c.stream, (const Ti*)in, (To*)out, a, ia, ib, ntA, ntB, scale);
+    // B: the output-innermost dim and those that follow it in the output,
+    // up to 64 elements, leaving the input-innermost dim to A; A: the
+    // trailing input dims not in B, up to 64 elements
+    PermTile p;
+    bool inb[kMaxDims] = {false}, ina[kMaxDims] = {false};
+    p.nb = 0;
+    p.B = 1;
+    for (int d = ib; d >= 0 && p.B < 64;) {
+      inb[d] = true;
+      p.bdim[p.nb] = a.dims[d];
+      p.bin[p.nb] = a.sin[d];
+      ++p.nb;
+      p.B *= a.dims[d];
+      const int64_t next = a.sout[d] * a.dims[d];
+      int nx = -1;
+      for (int e = 0; e < a.nd; ++e)
+        if (!inb[e] && e != ia && a.sout[e] == next && a.dims[e] > 1) nx = e;
+      d = nx;
+    }
+    p.na = 0;
+    p.A = 1;
+    for (int d = a.nd - 1; d >= 0 && !inb[d] && p.A < 64; --d) {
+      ina[d] = true;
+      p.adim[p.na] = a.dims[d];
+      p.aout[p.na] = a.sout[d];
+      ++p.na;
+      p.A *= a.dims[d];
+    }
+    p.nr = 0;
+    for (int d = 0; d < a.nd; ++d)
+      if (!ina[d] && !inb[d]) {
+        p.rdim[p.nr] = a.dims[d];
+        p.rin[p.nr] = a.sin[d];
+        p.rout[p.nr] = a.sout[d];
+        ++p.nr;
+      }
+    const int64_t ntA = (p.A + 63) / 64, ntB = (p.B + 63) / 64;
+    const int64_t blocks = ntA * ntB * (total / (p.A * p.B));
+    hipLaunchKernelGGL((permute_ctile_kernel<Ti, To>), dim3((unsigned)blocks), dim3(256), 0,
+                       c.stream, (const Ti*)in, (To*)out, p, ntA, ntB, scale);
   }
   c.check_launch();
 }
