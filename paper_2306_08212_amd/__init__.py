@@ -58,6 +58,9 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise FileNotFoundError(
             f"{path} not found: build it with `python -m paper_2306_08212_amd.build`")
+    # torch brings its own HIP runtime; load it first so that the library
+    # binds to that one instead of starting a second runtime in the process
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     P = ctypes.c_void_p
     I = ctypes.c_int

@@ -6,6 +6,8 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -82,7 +84,10 @@ struct Ctx {
   double* work = nullptr;     // device tallies of data-dependent work (profiling)
   uint64_t rng_calls = 0;     // counter of randomised truncations (seeds)
   void check(hipError_t e) {
-    if (e != hipSuccess && hip_err == hipSuccess) hip_err = e;
+    if (e != hipSuccess && hip_err == hipSuccess) {
+      hip_err = e;
+      if (std::getenv("CTM_DEBUG_HIP")) std::fprintf(stderr, "ctm: HIP error %s\n", hipGetErrorString(e));
+    }
   }
   void check_launch() { check(hipGetLastError()); }
   Tensor alloc(int dt, std::initializer_list<int64_t> dims);

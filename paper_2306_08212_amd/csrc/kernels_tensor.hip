@@ -61,23 +61,28 @@ __global__ __launch_bounds__(256) void permute_rows_kernel(const Ti* __restrict_
   }
 }
 
-// Composite tiles: A is the run of trailing input dims (contiguous in the
-// input, so its linear index is its input offset) and B the run of dims that
-// are innermost in the output (contiguous there, so its linear index is its
-// output offset).  A 64 x 64 tile over (A, B) reads 64 contiguous input
-// elements and writes 64 contiguous output elements per row even when the
-// individual innermost dims are short (bond dimension D), which a tile over
-// single dims cannot.  The other offset of each side comes from decomposing
-// the composite index once per workgroup.
+// Composite tiles.  When the innermost input leg is also innermost in the
+// output and shorter than 64 it is carried as a payload of P elements;
+// otherwise P = 1.  A is the run of input legs just above the payload
+// (contiguous in the input, so unit a sits at input offset a*P) and B the run
+// of legs just above the payload in the output (unit b at output offset b*P).
+// A tile holds TA units of A (TA*P <= 64 elements) by 64 units of B: every
+// read is a run of TA*P contiguous input elements and every write a run of
+// 64*P contiguous output elements, even when each leg is only as long as the
+// bond dimension D.  The other offset of each side comes from decomposing the
+// composite index once per workgroup.
 struct PermTile {
   int na, nb, nr;
-  int64_t A, B;
-  int64_t adim[kMaxDims], aout[kMaxDims];   // A dims, innermost first; output strides
-  int64_t bdim[kMaxDims], bin[kMaxDims];    // B dims, output-innermost first; input strides
-  int64_t rdim[kMaxDims], rin[kMaxDims], rout[kMaxDims];   // the other dims, outermost first
+  int P, TA;                                // TA = 64 / P
+  int64_t A, B;                             // lengths of the runs, in units
+  int64_t adim[kMaxDims], aout[kMaxDims];   // A legs, innermost first; output strides
+  int64_t bdim[kMaxDims], bin[kMaxDims];    // B legs, output-innermost first; input strides
+  int64_t rdim[kMaxDims], rin[kMaxDims], rout[kMaxDims];   // the other legs
 };
 
-template <typename Ti, typename To>
+// PP: the payload length when fixed at compile time (1, or the bond
+// dimension 8), 0 when it is read from p.P.
+template <typename Ti, typename To, int PP>
 __global__ __launch_bounds__(256) void permute_ctile_kernel(const Ti* __restrict__ in,
                                                              To* __restrict__ out, PermTile p,
                                                              int64_t ntA, int64_t ntB,
@@ -97,15 +102,17 @@ __global__ __launch_bounds__(256) void permute_ctile_kernel(const Ti* __restrict
     bo += cd * p.rout[d];
   }
   const int t = threadIdx.x;
-  if (t < 64) {
-    int64_t x = tA * 64 + t, o = 0;
+  const int P = PP ? PP : p.P;
+  const int TA = 64 / P;
+  if (t < TA) {
+    int64_t x = tA * TA + t, o = 0;
     for (int k = 0; k < p.na; ++k) {
       const int64_t q = x / p.adim[k];
       o += (x - q * p.adim[k]) * p.aout[k];
       x = q;
     }
     aoff_out[t] = o;
-  } else if (t < 128) {
+  } else if (t >= 64 && t < 128) {
     int64_t x = tB * 64 + (t - 64), o = 0;
     for (int k = 0; k < p.nb; ++k) {
       const int64_t q = x / p.bdim[k];
@@ -115,21 +122,28 @@ __global__ __launch_bounds__(256) void permute_ctile_kernel(const Ti* __restrict
     boff_in[t - 64] = o;
   }
   __syncthreads();
+  // read: row j of the tile is B unit tB*64 + j, column c element c of the
+  // A units tA*TA ... (TA*P contiguous input elements)
   const int tx = t & 63, ty = t >> 6;
-  const int64_t xa = tA * 64 + tx;
+  const int W = TA * P;
+  const int64_t abase = tA * TA;
+  const bool cin = tx < W && abase + tx / P < p.A;
+  const int64_t ioff = bi + abase * P + tx;
 #pragma unroll 4
   for (int j = ty; j < 64; j += 4) {
-    const int64_t xb = tB * 64 + j;
     double v = 0.0;
-    if (xa < p.A && xb < p.B) v = ld(in, bi + xa + boff_in[j]);
+    if (cin && tB * 64 + j < p.B) v = ld(in, ioff + boff_in[j]);
     tile[j][tx] = v;
   }
   __syncthreads();
-  const int64_t yb = tB * 64 + tx;
+  // write: A unit al gets 64*P contiguous output elements
+  const int R = 64 * P;
 #pragma unroll 4
-  for (int j = ty; j < 64; j += 4) {
-    const int64_t ya = tA * 64 + j;
-    if (ya < p.A && yb < p.B) st(out, bo + aoff_out[j] + yb, tile[tx][j] * scale);
+  for (int w = t; w < TA * R; w += 256) {
+    const int al = w / R, rem = w - al * R;
+    const int b = rem / P, e = rem - b * P;
+    const int64_t ya = abase + al, yb = tB * 64 + b;
+    if (ya < p.A && yb < p.B) st(out, bo + aoff_out[al] + yb * P + e, tile[b][al * P + e] * scale);
   }
 }
 
@@ -143,20 +157,28 @@ void launch_permute(Ctx& c, const void* in, void* out, const PermArgs& a, double
   for (int d = 0; d < a.nd; ++d)
     if (a.sout[d] == 1 && a.dims[d] > 1) ib = d;
   const int ia = a.nd - 1;
-  if (a.nd == 1 || ib == ia || a.dims[ib] == 1) {
+  const bool shared = ib == ia || a.dims[ib] == 1;
+  if (a.nd == 1 || (shared && a.dims[ia] >= 64)) {
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL((permute_rows_kernel<Ti, To>), dim3((unsigned)blocks), dim3(256), 0,
                        c.stream, (const Ti*)in, (To*)out, a, total, scale);
   } else {
-    // B: the output-innermost dim and those that follow it in the output,
-    // up to 64 elements, leaving the input-innermost dim to A; A: the
-    // trailing input dims not in B, up to 64 elements
+    // payload: the shared innermost leg (if any); B: the leg just above the
+    // payload in the output and those that follow it there, up to 64 units,
+    // leaving the leg just above the payload in the input to A; A: the input
+    // legs above the payload not in B, up to 64 elements with the payload
     PermTile p;
+    const int top = shared ? ia - 1 : ia;   // innermost leg of A
+    p.P = shared ? (int)a.dims[ia] : 1;
     bool inb[kMaxDims] = {false}, ina[kMaxDims] = {false};
+    int start = -1;
+    for (int d = 0; d < a.nd; ++d)
+      if (d != ia || !shared)
+        if (a.sout[d] == p.P && a.dims[d] > 1) start = d;
     p.nb = 0;
     p.B = 1;
-    for (int d = ib; d >= 0 && p.B < 64;) {
+    for (int d = start; d >= 0 && p.B < 64;) {
       inb[d] = true;
       p.bdim[p.nb] = a.dims[d];
       p.bin[p.nb] = a.sin[d];
@@ -165,12 +187,12 @@ void launch_permute(Ctx& c, const void* in, void* out, const PermArgs& a, double
       const int64_t next = a.sout[d] * a.dims[d];
       int nx = -1;
       for (int e = 0; e < a.nd; ++e)
-        if (!inb[e] && e != ia && a.sout[e] == next && a.dims[e] > 1) nx = e;
+        if (!inb[e] && e != top && a.sout[e] == next && a.dims[e] > 1) nx = e;
       d = nx;
     }
     p.na = 0;
     p.A = 1;
-    for (int d = a.nd - 1; d >= 0 && !inb[d] && p.A < 64; --d) {
+    for (int d = top; d >= 0 && !inb[d] && p.A * p.P < 64; --d) {
       ina[d] = true;
       p.adim[p.na] = a.dims[d];
       p.aout[p.na] = a.sout[d];
@@ -178,17 +200,25 @@ void launch_permute(Ctx& c, const void* in, void* out, const PermArgs& a, double
       p.A *= a.dims[d];
     }
     p.nr = 0;
-    for (int d = 0; d < a.nd; ++d)
+    for (int d = 0; d < top + 1; ++d)
       if (!ina[d] && !inb[d]) {
         p.rdim[p.nr] = a.dims[d];
         p.rin[p.nr] = a.sin[d];
         p.rout[p.nr] = a.sout[d];
         ++p.nr;
       }
-    const int64_t ntA = (p.A + 63) / 64, ntB = (p.B + 63) / 64;
-    const int64_t blocks = ntA * ntB * (total / (p.A * p.B));
-    hipLaunchKernelGGL((permute_ctile_kernel<Ti, To>), dim3((unsigned)blocks), dim3(256), 0,
-                       c.stream, (const Ti*)in, (To*)out, p, ntA, ntB, scale);
+    p.TA = 64 / p.P;
+    const int64_t ntA = (p.A + p.TA - 1) / p.TA, ntB = (p.B + 63) / 64;
+    const dim3 grid((unsigned)(ntA * ntB * (total / (p.A * p.B * p.P))));
+    if (p.P == 1)
+      hipLaunchKernelGGL((permute_ctile_kernel<Ti, To, 1>), grid, dim3(256), 0, c.stream,
+                         (const Ti*)in, (To*)out, p, ntA, ntB, scale);
+    else if (p.P == 8)
+      hipLaunchKernelGGL((permute_ctile_kernel<Ti, To, 8>), grid, dim3(256), 0, c.stream,
+                         (const Ti*)in, (To*)out, p, ntA, ntB, scale);
+    else
+      hipLaunchKernelGGL((permute_ctile_kernel<Ti, To, 0>), grid, dim3(256), 0, c.stream,
+                         (const Ti*)in, (To*)out, p, ntA, ntB, scale);
   }
   c.check_launch();
 }

@@ -65,7 +65,11 @@ def test_gemm_beta_accumulates():
                                          ((4, 5, 6, 7, 8, 3), (5, 4, 3, 2, 1, 0)),
                                          ((100, 1, 37), (2, 1, 0)), ((1000,), (0,)),
                                          ((70, 3, 130), (2, 1, 0)),
-                                         ((3, 96, 2, 130), (0, 3, 2, 1))])
+                                         ((3, 96, 2, 130), (0, 3, 2, 1)),
+                                         ((6, 5, 7, 3), (0, 2, 1, 3)),
+                                         ((3, 70, 40, 33), (0, 2, 1, 3)),
+                                         ((5, 40, 96, 2, 8), (0, 2, 3, 1, 4)),
+                                         ((16, 70, 2, 8), (2, 1, 0, 3))])
 def test_permute_and_cast(shape, perm):
     log("permute", shape, perm)
     t = torch()
