@@ -223,15 +223,15 @@ def main():
     # GEMMs in TFLOP/s (fraction of their dtype's dense peak), memory-bound
     # classes in GB/s (fraction of 8 TB/s)
     for k, rec in breakdown.items():
-        n_, kms, kfl, kby = prof[k]
-        if kms <= 0:
+        _, c_ms, c_fl, c_by = prof[k]
+        if c_ms <= 0:
             continue
-        if k.startswith("gemm") and kfl > 0:
-            tf = kfl / (kms / 1e3) / 1e12
+        if k.startswith("gemm") and c_fl > 0:
+            tf = c_fl / (c_ms / 1e3) / 1e12
             rec["tflops"] = tf
             rec["frac_of_peak"] = tf / (PEAK[k][0] / 1e12)
-        elif k in ("permute", "copy", "reduce") and kby > 0:
-            gbs = kby / (kms / 1e3) / 1e9
+        elif k in ("permute", "copy", "reduce") and c_by > 0:
+            gbs = c_by / (c_ms / 1e3) / 1e9
             rec["gb_per_s"] = gbs
             rec["frac_of_peak"] = gbs / 8000.0
     gemm_flops = sum(prof[k][2] for k in ("gemm_f64", "gemm_f32", "gemm_bf16")) / nprof
