@@ -85,6 +85,23 @@ def test_permute_and_cast(shape, perm):
     assert np.array_equal(yb, refb)
 
 
+@pytest.mark.parametrize("shape,perm", [((256, 8, 256, 8, 8), (0, 1, 3, 2, 4)),
+                                        ((8, 256, 256, 2, 8, 8), (0, 2, 3, 4, 1, 5)),
+                                        ((8, 2, 8, 256, 8, 256), (5, 4, 0, 1, 2, 3)),
+                                        ((256, 8, 8, 2, 8, 256), (0, 4, 5, 3, 2, 1))])
+def test_permute_move_shapes_f32(shape, perm):
+    """Full-size permutes of the FP32 absorption chains at D=8, chi=256 (the
+    D-leg payload tile and the composite tile), bitwise against a CPU
+    transpose."""
+    log("permute f32", shape, perm)
+    t = torch()
+    g = t.Generator().manual_seed(7)
+    x = t.randn(shape, generator=g, dtype=t.float32)
+    ref = x.permute(perm).contiguous()
+    y = permute(x.to("cuda"), perm, 1, 1).cpu()
+    assert t.equal(y, ref)
+
+
 def _graded(m, n, decay, seed):
     k = min(m, n)
     U = random_orthogonal(m, seed)[:, :k]
