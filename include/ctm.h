@@ -27,8 +27,12 @@
  *   initial environment) and grow to at most chi.
  *
  * Errors: every function returns a ctm_status (CTM_OK = 0); nothing throws
- * across this interface.  All functions taking a solver enqueue work on the
- * solver's stream and return without waiting unless stated otherwise.
+ * across this interface.  With the environment variable CTM_DEBUG_HIP set,
+ * the first failing HIP call of an operation is also named on stderr.  The
+ * library must use the same HIP runtime as the caller's device buffers (with
+ * PyTorch: load torch before this library).  All functions taking a solver
+ * enqueue work on the solver's stream and return without waiting unless
+ * stated otherwise.
  */
 #ifndef CTM_H
 #define CTM_H
