@@ -11,6 +11,9 @@
 // written outside [0,m) x [0,n).
 #include <algorithm>
 
+#include <cstdio>
+#include <cstdlib>
+
 #include "ctm_internal.h"
 
 namespace ctm {
@@ -299,6 +302,9 @@ void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A, i
           int batch, int64_t sA, int64_t sB, int64_t sC) {
   if (m <= 0 || n <= 0 || batch <= 0) return;
   if (k < 0) k = 0;
+  if (std::getenv("CTM_DEBUG_GEMM") && (double)m * n * k * batch >= 1e9 && !c.dry)
+    std::fprintf(stderr, "gemm dt %d m %d n %d k %d batch %d ta %d tb %d\n", dtype, m, n, k, batch,
+                 ta, tb);
   // FP64 grids that cannot fill the chip split K (partials in the arena,
   // summed in a fixed order by a second pass, so results stay bitwise
   // reproducible)
