@@ -54,6 +54,119 @@ def test_random_product_state_energy(seed):
         assert abs(r["e_site"] - 2 * exact) < 1e-13
 
 
+# ------------------------------------------------------------ operators
+
+def _spin_ops():
+    """Spin-1/2 operators S = sigma / 2 as complex matrices, written from
+    the Pauli matrices (not from the oracle's real form of S.S)."""
+    sx = np.array([[0, 1], [1, 0]], dtype=complex) / 2
+    sy = np.array([[0, -1j], [1j, 0]], dtype=complex) / 2
+    sz = np.array([[1, 0], [0, -1]], dtype=complex) / 2
+    return sx, sy, sz
+
+
+def test_heisenberg_h2_spectrum():
+    """S.S on two spins 1/2: singlet -3/4, triplet +1/4 (three times), from
+    S_tot^2 = s(s+1) with S_1.S_2 = (S_tot^2 - 3/2) / 2.  A wrong sign on
+    any of the three terms moves an eigenvalue (e.g. -S^yS^y gives
+    {-1/4, -1/4, -1/4, 3/4})."""
+    h = O.heisenberg_h2()
+    assert h.shape == (4, 4)
+    np.testing.assert_allclose(h, h.T, atol=0)
+    np.testing.assert_allclose(np.linalg.eigvalsh(h), [-0.75, 0.25, 0.25, 0.25], atol=1e-15)
+
+
+def test_heisenberg_h2_singlet_and_triplet_states():
+    """<h> on the two-site singlet (|ud> - |du>)/sqrt2 is -3/4, on the
+    triplet states |uu>, (|ud> + |du>)/sqrt2 and |dd> it is +1/4 (basis
+    order (s1 s2) with s = 0 up, 1 down)."""
+    h = O.heisenberg_h2()
+    r2 = np.sqrt(0.5)
+    singlet = np.array([0.0, r2, -r2, 0.0])
+    t0 = np.array([0.0, r2, r2, 0.0])
+    assert abs(singlet @ h @ singlet + 0.75) < 1e-15
+    assert abs(t0 @ h @ t0 - 0.25) < 1e-15
+    for i in (0, 3):
+        e = np.zeros(4); e[i] = 1.0
+        assert abs(e @ h @ e - 0.25) < 1e-15
+
+
+def test_heisenberg_h2_equals_spin_dot_product_and_is_su2_invariant():
+    """h equals S_1.S_2 built from the complex Pauli matrices, and commutes
+    with every component of the total spin (SU(2) invariance)."""
+    sx, sy, sz = _spin_ops()
+    ref = sum(np.kron(a, a) for a in (sx, sy, sz))
+    assert np.abs(ref.imag).max() == 0.0
+    h = O.heisenberg_h2()
+    np.testing.assert_allclose(h, ref.real, atol=1e-16)
+    one = np.eye(2)
+    for a in (sx, sy, sz):
+        tot = np.kron(a, one) + np.kron(one, a)
+        assert np.abs(h @ tot - tot @ h).max() < 1e-15
+
+
+# ------------------------------------------------------------ convergence measure
+
+def _env_with_corner_spectra(chi, spectra, seed=0):
+    """An environment whose 8 corners have the given singular values (in a
+    random orthogonal basis on each side); edges are unused."""
+    env = {}
+    for i, key in enumerate(OC.CORNERS):
+        s = np.asarray(spectra[i], dtype=float)
+        n = s.size
+        U = random_orthogonal(n, seed + 2 * i)
+        V = random_orthogonal(n, seed + 2 * i + 1)
+        env[key] = U @ np.diag(s) @ V.T
+    return env
+
+
+def test_corner_spectra_known_values():
+    """Normalised by the largest singular value and zero padded to chi:
+    singular values (3, 2, 1) at chi = 5 give (1, 2/3, 1/3, 0, 0)."""
+    spectra = [[3.0, 2.0, 1.0]] * 8
+    sp = O.corner_spectra(_env_with_corner_spectra(5, spectra), 5)
+    for key in OC.CORNERS:
+        np.testing.assert_allclose(sp[key], [1.0, 2.0 / 3.0, 1.0 / 3.0, 0.0, 0.0], atol=1e-15)
+
+
+def test_corner_spectra_scale_invariant_and_truncated_to_chi():
+    """Each corner's spectrum is divided by its own sigma_0 (scaling one
+    corner changes nothing) and cut to chi entries when the corner is
+    larger."""
+    spectra = [[4.0, 1.0, 0.5, 0.25]] * 4 + [[8.0, 2.0, 1.0, 0.5]] * 4
+    env = _env_with_corner_spectra(3, spectra, seed=5)
+    sp = O.corner_spectra(env, 3)
+    for key in OC.CORNERS:
+        np.testing.assert_allclose(sp[key], [1.0, 0.25, 0.125], atol=1e-15)
+    env2 = dict(env)
+    env2["C3b"] = 17.0 * env["C3b"]
+    sp2 = O.corner_spectra(env2, 3)
+    np.testing.assert_allclose(sp2["C3b"], sp["C3b"], atol=1e-15)
+
+
+def test_solve_delta_is_max_change_of_normalised_spectra():
+    """solve's delta after an iteration is the largest change of a
+    normalised corner singular value, and solve stops at the first
+    iteration whose delta is below tol.  The Onsager Ising state converges
+    (a fixed point), so delta falls below 1e-11 and stays there."""
+    A = _ising_peps(0.3)
+    zz = np.kron(np.diag([1.0, -1.0]), np.diag([1.0, -1.0]))
+    r = O.solve(A, A, 12, O.STANDARD, max_iters=40, tol=1e-11, h2=zz)
+    assert r["delta"] < 1e-11 and r["iters"] < 40
+    assert all(d >= 1e-11 for d in r["deltas"][:-1])
+    # one more iteration from the fixed point: delta recomputed by hand
+    env0 = r["env"]
+    env1 = O.ctm_iteration(env0, A, A, 12, O.STANDARD)
+    dl = 0.0
+    for key in OC.CORNERS:
+        s0 = np.linalg.svd(env0[key], compute_uv=False)
+        s1 = np.linalg.svd(env1[key], compute_uv=False)
+        v0 = np.zeros(12); v0[:min(12, s0.size)] = (s0 / s0[0])[:12]
+        v1 = np.zeros(12); v1[:min(12, s1.size)] = (s1 / s1[0])[:12]
+        dl = max(dl, np.abs(v1 - v0).max())
+    assert dl < 1e-11
+
+
 # ------------------------------------------------------------ brute force
 
 def _bf_all(A, B, h2, nL, nR, nU, nD):
