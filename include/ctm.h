@@ -47,10 +47,17 @@ typedef struct ctm_solver ctm_solver; /* opaque, owned by the library */
 
 enum ctm_status {
   CTM_OK = 0,
-  CTM_EINVAL = 1,    /* bad argument (dimension < 1, NULL pointer, bad enum) */
-  CTM_ENOMEM = 2,    /* workspace smaller than ctm_workspace_size()         */
-  CTM_EHIP = 3,      /* a HIP runtime call failed                            */
-  CTM_ENUMERIC = 4,  /* a tensor norm was zero, NaN or Inf                   */
+  CTM_EINVAL = 1,    /* bad argument (d < 2, D < 1, chi < D^2, NULL pointer,
+                        bad enum)                                            */
+  CTM_ENOMEM = 2,    /* workspace smaller than ctm_workspace_size(), or a
+                        host allocation failed                              */
+  CTM_EHIP = 3,      /* a HIP runtime call failed (including a failed graph
+                        capture of a move)                                  */
+  CTM_ENUMERIC = 4,  /* a tensor norm was zero, NaN or Inf, or a Jacobi SVD
+                        of a truncation did not converge within its sweep
+                        cap; reported by the next synchronising call
+                        (ctm_converge, ctm_read_delta, ctm_energy) and kept
+                        for the solver's lifetime                           */
   CTM_ENOTCONV = 5   /* ctm_converge reached max_iters; state stays valid    */
 };
 
@@ -70,7 +77,8 @@ enum ctm_dir { CTM_LEFT = 0, CTM_UP = 1, CTM_RIGHT = 2, CTM_DOWN = 3 };
 typedef struct {
   int d;                 /* physical dimension (>= 2)                         */
   int D;                 /* virtual bond dimension (>= 1)                     */
-  int chi;               /* boundary dimension (>= 1)                         */
+  int chi;               /* boundary dimension chi (>= D^2: the traced-boundary
+                            environment starts with bonds of dimension D^2)  */
   int method;            /* enum ctm_method                                   */
   int precision;         /* enum ctm_precision                                */
   int boot_iters;        /* leading iterations that use standard isometries
@@ -87,21 +95,40 @@ typedef struct {
  * Host-only; returns 0 for an invalid cfg. */
 size_t ctm_workspace_size(const ctm_config *cfg);
 
-/* Create a solver: copies A and B (host or device pointers, ptrs_on_device),
- * builds the traced-boundary environment and normalises it.  *out receives
- * the handle; free it with ctm_destroy.  Synchronises the stream once. */
+/* Create a solver for the problem of Sec. II: the two-site unit cell {A, B}
+ * of 5-index site tensors (d, D, D, D, D) and the 16 environment tensors
+ * {C^i_z, T^i_z} of boundary dimension chi (Fig. 1(d)).  Copies A and B
+ * (host or device pointers, ptrs_on_device; the caller keeps its buffers),
+ * builds the initial environment -- the paper does not state one; here each
+ * tensor is the single boundary site it stands for with its outward legs
+ * traced (ket = bra), bonds D^2 -- and normalises it.  *out receives the
+ * handle; free it with ctm_destroy.  Synchronises the stream once.
+ * CTM_EINVAL for a bad cfg (d < 2, D < 1, chi < D^2, unknown method or
+ * precision) or NULL pointers, CTM_ENOMEM when cfg->workspace_bytes is below
+ * ctm_workspace_size(cfg), CTM_EHIP for a failed HIP call. */
 int ctm_init(const ctm_config *cfg, const double *A, const double *B, int ptrs_on_device,
              ctm_solver **out);
 
-/* One directional move (two column insertions, Sec. II) in direction dir. */
+/* One directional move (Sec. II, Fig. 2(a,b)): two column insertions, each
+ * absorbing {T^2, site, site, T^4} into the left environment and truncating
+ * the enlarged bonds with the isometries of the solver's method -- standard
+ * (Sec. II, Fig. 2(c)) or sequential-order (Secs. III-IV, Figs. 3-4, App.).
+ * The other directions are the left move in a frame turned dir quarter
+ * turns (Sec. II, "moves in other directions can be adjusted
+ * accordingly").  Asynchronous; CTM_EINVAL for a bad dir. */
 int ctm_move(ctm_solver *s, int dir);
 
 /* n full iterations (moves left, right, up, down) with no host round trip. */
 int ctm_iterate(ctm_solver *s, int n);
 
-/* Iterate until the normalised corner spectra change by less than tol
- * (max abs over the 8 corners) or max_iters iterations; reads one scalar
- * per iteration (synchronises).  iters_done/delta may be NULL. */
+/* Iterate the four moves until converged (Sec. II: N_CTM ~ 10-30 iterations
+ * of moves in four directions).  The paper gives no convergence measure;
+ * here it is delta = the largest change, over the 8 corners, of a corner's
+ * singular values divided by its largest one, zero padded to chi.  Stops
+ * when delta < tol (CTM_OK) or after max_iters iterations (CTM_ENOTCONV;
+ * the state stays valid).  Reads one scalar per iteration (synchronises).
+ * iters_done / delta may be NULL.  CTM_ENUMERIC if a norm failed or an SVD
+ * did not converge. */
 int ctm_converge(ctm_solver *s, int max_iters, double tol, int *iters_done, double *delta);
 
 /* One full iteration followed by the corner-spectrum change delta, all
@@ -111,12 +138,18 @@ int ctm_converge(ctm_solver *s, int max_iters, double tol, int *iters_done, doub
 int ctm_iterate_delta(ctm_solver *s);
 int ctm_read_delta(ctm_solver *s, double *delta);
 
-/* Bond energies <h> of the four bond types and the per-site energy
- * e_site = (sum of e_bond) / 2.  h2 is a host d^2 x d^2 row-major operator
- * h[(s1 s2)][(s1' s2')] acting on (left, right) or (top, bottom) sites, or
- * NULL for S.S with S = sigma / 2.  e_bond order: horizontal (a left of b),
- * horizontal (b left of a), vertical (a above b), vertical (b above a).
- * Synchronises the stream. */
+/* Bond energies of Sec. V, Eq. (1): e_bond = Tr(rho h) / Tr(rho) with rho
+ * the two-site reduced density matrix of a nearest-neighbour bond contracted
+ * from the environment (a 2 x 4 network: the two sites between their edges
+ * and corners), for the four bond types, and the per-site energy
+ * e_site = (sum of e_bond) / 2 (two bonds per site).  h2 is a host d^2 x d^2
+ * row-major operator h[(s1 s2)][(s1' s2')] acting on (left, right) or
+ * (top, bottom) sites, or NULL for S.S with S = sigma / 2 -- Eq. (1) prints
+ * -S.S "with Pauli matrices", but the quoted QMC energy -0.669437 is that of
+ * the spin-1/2 antiferromagnet +S.S, S = sigma / 2, which is used here.
+ * e_bond order: horizontal (a left of b), horizontal (b left of a), vertical
+ * (a above b), vertical (b above a).  Synchronises the stream.  CTM_ENUMERIC
+ * for a non-finite or zero-trace result or a pending numeric error. */
 int ctm_energy(ctm_solver *s, const double *h2, double *e_site, double e_bond[4]);
 
 /* Copy environment tensor e (0..15, see above) to host memory: writes its two

@@ -32,7 +32,11 @@ int ctm_kernel_gemm(int dtype, int m, int n, int k, double alpha, const void *A,
  * zeroed; each kept column is sign-fixed (lowest row within 1e-8 relative of
  * the largest magnitude is positive).  M is not modified.  workspace is
  * caller-owned device memory of at least ctm_kernel_tsvd_workspace(m, n, k)
- * bytes.  CTM_ENOMEM if it is smaller. */
+ * bytes.  CTM_ENOMEM if it is smaller.  Unlike the other calls this one
+ * synchronises the stream at the end, to read the solver's error word:
+ * CTM_ENUMERIC when a Jacobi solve inside did not converge within its sweep
+ * cap (the outputs are then an orthonormal basis that is not the top-k
+ * singular subspace). */
 int ctm_kernel_tsvd(const double *M, int m, int n, int k, double tau, double *U, double *S,
                     void *workspace, size_t workspace_bytes, void *stream);
 size_t ctm_kernel_tsvd_workspace(int m, int n, int k);

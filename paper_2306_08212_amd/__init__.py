@@ -241,6 +241,15 @@ class Solver:
         _check(load().ctm_set_env(self.handle, e, t.ctypes.data, t.shape[0], t.shape[-1]),
                "ctm_set_env")
 
+    def get_env_dict(self) -> dict:
+        """All 16 environment tensors as {name: array} (names of ENV_NAMES)."""
+        return {n: self.get_env(env_index(n)) for n in ENV_NAMES}
+
+    def set_env_dict(self, env: dict):
+        """Replace environment tensors from {name: array} (warm start)."""
+        for n, t in env.items():
+            self.set_env(env_index(n), t)
+
     @property
     def moves_done(self) -> int:
         return load().ctm_moves_done(self.handle)

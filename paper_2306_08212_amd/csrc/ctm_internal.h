@@ -8,12 +8,20 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstdlib>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
 namespace ctm {
 
 enum DType : int { F64 = 0, F32 = 1, BF16 = 2 };
+
+// An error that carries the ctm_status the C-ABI returns for it (workspace
+// exhausted, a failed HIP call such as a graph capture).
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const char* what) : std::runtime_error(what), code(c) {}
+};
 
 inline size_t dtype_size(int dt) { return dt == F64 ? 8 : (dt == F32 ? 4 : 2); }
 
@@ -40,7 +48,9 @@ Tensor make_view(void* p, int dt, const std::vector<int64_t>& dims);
 
 // Bump allocator over caller-owned device memory.  In dry-run mode it only
 // tracks the high-water mark; pointers are offsets from a fake base and no
-// kernel is launched.
+// kernel is launched.  Outside dry runs an allocation beyond the capacity
+// sets `overflow` and throws Error(CTM_ENOMEM = 2), so no kernel is ever
+// launched on memory the arena does not own.
 struct Arena {
   char* base = nullptr;
   size_t cap = 0;
@@ -80,7 +90,7 @@ struct Ctx {
   Arena arena;
   bool dry = false;
   hipError_t hip_err = hipSuccess;
-  int* dev_flags = nullptr;   // [0] numeric error, [1..] scratch counters
+  int* dev_flags = nullptr;   // [0] numeric error bits (1 bad norm, 2 SVD not converged)
   double* work = nullptr;     // device tallies of data-dependent work (profiling)
   uint64_t rng_calls = 0;     // counter of randomised truncations (seeds)
   void check(hipError_t e) {

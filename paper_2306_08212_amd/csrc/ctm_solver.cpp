@@ -190,7 +190,7 @@ void run_branches(ctm_solver* s, const std::vector<std::function<void(Ctx&)>>& f
       k.check(hipStreamEndCapture(k.stream, &g));
       if (g != nullptr && k.hip_err == hipSuccess) k.check(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0));
       if (g) (void)hipGraphDestroy(g);
-      if (ex == nullptr) throw std::runtime_error("branch capture failed");
+      if (ex == nullptr) throw Error(CTM_EHIP, "branch capture failed");
       s->gexec[key] = ex;
       k.check(hipGraphLaunch(ex, k.stream));
     } else {
@@ -742,6 +742,22 @@ void setup(ctm_solver* s, const double* A, const double* B, int on_device) {
   }
 }
 
+// Status for the exception being handled (call inside a catch block):
+// the code an Error carries, CTM_ENOMEM for a failed host allocation, and
+// otherwise CTM_EHIP when a HIP call has failed, CTM_EINVAL if not.
+int fail_status(const ctm_solver* s) {
+  try {
+    throw;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    return CTM_ENOMEM;
+  } catch (...) {
+    if (s && s->ctx.hip_err != hipSuccess) return CTM_EHIP;
+    return CTM_EINVAL;
+  }
+}
+
 int status_from(ctm_solver* s) {
   if (s->ctx.arena.overflow) return CTM_ENOMEM;
   if (s->ctx.hip_err != hipSuccess) return CTM_EHIP;
@@ -751,6 +767,8 @@ int status_from(ctm_solver* s) {
 bool valid_cfg(const ctm_config* cfg) {
   if (!cfg) return false;
   if (cfg->d < 2 || cfg->D < 1 || cfg->chi < 1) return false;
+  // the traced-boundary environment starts with bonds of dimension D^2
+  if ((int64_t)cfg->chi < (int64_t)cfg->D * cfg->D) return false;
   if (cfg->method != CTM_STANDARD && cfg->method != CTM_REDUCED) return false;
   if (cfg->precision < CTM_FP64 || cfg->precision > CTM_BF16) return false;
   if (cfg->boot_iters < 0) return false;
@@ -769,7 +787,7 @@ void fill_from_cfg(ctm_solver* s, const ctm_config* cfg) {
   s->precision = cfg->precision;
   s->boot_iters = cfg->boot_iters;
   s->tau = cfg->svd_cutoff;
-  s->cap = std::max(cfg->chi, cfg->D * cfg->D);
+  s->cap = cfg->chi;   // valid_cfg requires chi >= D^2
   s->ctx.stream = (hipStream_t)cfg->stream;
 }
 
@@ -838,8 +856,9 @@ int ctm_init(const ctm_config* cfg, const double* A, const double* B, int ptrs_o
       return st;
     }
   } catch (...) {
+    const int st = fail_status(s);
     delete s;
-    return CTM_EINVAL;
+    return st;
   }
   *out = s;
   return CTM_OK;
@@ -850,7 +869,7 @@ int ctm_move(ctm_solver* s, int dir) {
   try {
     run_move(s, dir);
   } catch (...) {
-    return CTM_EINVAL;
+    return fail_status(s);
   }
   s->spec_valid = false;
   return status_from(s);
@@ -861,7 +880,7 @@ int ctm_iterate(ctm_solver* s, int n) {
   try {
     for (int i = 0; i < n; ++i) do_iteration(s);
   } catch (...) {
-    return CTM_EINVAL;
+    return fail_status(s);
   }
   s->spec_valid = false;
   return status_from(s);
@@ -896,7 +915,7 @@ int ctm_converge(ctm_solver* s, int max_iters, double tol, int* iters_done, doub
       if (dl < tol) break;
     }
   } catch (...) {
-    return CTM_EINVAL;
+    return fail_status(s);
   }
   if (iters_done) *iters_done = it;
   if (delta) *delta = dl;
@@ -918,7 +937,7 @@ int ctm_iterate_delta(ctm_solver* s) {
     corner_spectra(s);
     max_abs_diff(c, s->spec[s->spec_cur], s->spec[s->spec_cur ^ 1], 8 * s->chi, s->scal + 32);
   } catch (...) {
-    return CTM_EINVAL;
+    return fail_status(s);
   }
   return status_from(s);
 }
@@ -959,7 +978,7 @@ int ctm_energy(ctm_solver* s, const double* h2, double* e_site, double e_bond[4]
     c.check(hipMemcpyAsync(&flag, c.dev_flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
     c.check(hipStreamSynchronize(c.stream));
   } catch (...) {
-    return CTM_EINVAL;
+    return fail_status(s);
   }
   const int st = status_from(s);
   if (st != CTM_OK) return st;
@@ -1066,7 +1085,7 @@ const char* ctm_status_string(int status) {
     case CTM_EINVAL: return "invalid argument";
     case CTM_ENOMEM: return "workspace too small";
     case CTM_EHIP: return "HIP runtime error";
-    case CTM_ENUMERIC: return "numerical failure (zero, NaN or Inf norm)";
+    case CTM_ENUMERIC: return "numerical failure (zero, NaN or Inf norm, or a Jacobi SVD that did not converge)";
     case CTM_ENOTCONV: return "not converged within max_iters";
     default: return "unknown status";
   }

@@ -18,12 +18,21 @@ int ctm_kernel_gemm(int dtype, int m, int n, int k, double alpha, const void* A,
   return c.hip_err == hipSuccess ? CTM_OK : CTM_EHIP;
 }
 
+// The truncation with its error word (one int in the workspace, cleared
+// first): set when a Jacobi solve did not converge.
+static void tsvd_flagged(Ctx& c, const double* M, int m, int n, int k, double tau, double* U,
+                         double* S) {
+  c.dev_flags = (int*)c.arena.alloc(sizeof(int) * 4);
+  if (!c.dry) fill(c, c.dev_flags, F32, 4, 0.0);   // zero bit pattern
+  tsvd(c, M, m, n, k, tau, U, S);
+}
+
 size_t ctm_kernel_tsvd_workspace(int m, int n, int k) {
   if (m < 1 || n < 1 || k < 1) return 0;
   Ctx c;
   c.dry = true;
   c.arena.dry = true;
-  tsvd(c, nullptr, m, n, k, 0.0, nullptr, nullptr);
+  tsvd_flagged(c, nullptr, m, n, k, 0.0, nullptr, nullptr);
   return c.arena.peak + 256;
 }
 
@@ -35,9 +44,18 @@ int ctm_kernel_tsvd(const double* M, int m, int n, int k, double tau, double* U,
   c.stream = (hipStream_t)stream;
   c.arena.base = (char*)workspace;
   c.arena.cap = workspace_bytes;
-  tsvd(c, M, m, n, k, tau, U, S);
-  if (c.arena.overflow) return CTM_ENOMEM;
-  return c.hip_err == hipSuccess ? CTM_OK : CTM_EHIP;
+  try {
+    tsvd_flagged(c, M, m, n, k, tau, U, S);
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return c.hip_err == hipSuccess ? CTM_EINVAL : CTM_EHIP;
+  }
+  int flag = 0;
+  c.check(hipMemcpyAsync(&flag, c.dev_flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  c.check(hipStreamSynchronize(c.stream));
+  if (c.hip_err != hipSuccess) return CTM_EHIP;
+  return flag ? CTM_ENUMERIC : CTM_OK;
 }
 
 int ctm_kernel_permute(int dt_in, const void* in, int nd, const int64_t* dims, const int* perm,

@@ -13,9 +13,10 @@
 //   values are the column norms of X and the left singular vectors are the
 //   accumulated rotations mapped through Q (orthonormal by construction).
 //   The triangular factor of a norm-ordered QR has rows of decreasing size,
-//   which makes its transpose nearly column-orthogonal: the Jacobi sweeps
-//   then converge in a few sweeps even for strongly graded spectra, where on
-//   M itself they crawl.  A wide M (m < n) is first reduced to the square
+//   which makes its transpose closer to column-orthogonal than M; two more
+//   norm-ordered QR steps of the square factor (R^T = Q' R', then again)
+//   push it further toward diagonal, and the sweeps then converge in about
+//   five even for strongly graded spectra, where on M itself they crawl.  A wide M (m < n) is first reduced to the square
 //   L = M Q_1 from the QR of M^T, which has the same left singular vectors.
 //
 // Stopping test for a pair of columns a, b with Gram entries g_aa, g_bb, g_ab:
@@ -320,6 +321,13 @@ __global__ void jac_sweep_end(int* flags) {
     if (flags[0] == 0) flags[2] += 1;   // sweeps that rotated something
     flags[1] = 0;
   }
+}
+
+// After the last sweep: a Jacobi solve whose final sweep still rotated has
+// not converged; bit 2 of the solver's numeric error word records it (the
+// word is only ever set, never cleared, by kernels).
+__global__ void jac_converged_check(const int* __restrict__ flags, int* __restrict__ err) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && flags[0] == 0) err[0] |= 2;
 }
 
 __global__ void jac_flags_init(int* flags) {
@@ -1056,9 +1064,28 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
   int* flags = (int*)c.arena.alloc(4 * sizeof(int));
   double* fro = (double*)c.arena.alloc(sizeof(double));
   double* Uj = (double*)c.arena.alloc(sizeof(double) * (size_t)n * kk);
+  double* A1 = (double*)c.arena.alloc(sizeof(double) * (size_t)n * n);
+  double* Q2 = (double*)c.arena.alloc(sizeof(double) * (size_t)n * n);
+  double* A2 = (double*)c.arena.alloc(sizeof(double) * (size_t)n * n);
+  double* Q3 = (double*)c.arena.alloc(sizeof(double) * (size_t)n * n);
   orth_sorted(c, M, m, n, Q);
-  // X (column-major, n rows) = R^T = M^T Q, i.e. row-major Q^T M
-  gemm(c, F64, n, n, m, 1.0, Q, n, 1, M, n, 0, 0.0, X, n);
+  // Preconditioning (all matrices row-major).  M P1 = Q R1 with the column
+  // order P1 of orth_sorted; A1 = M^T Q = P1 R1^T, so M = Q A1^T.  Two more
+  // norm-ordered QR steps of the square factor: A1 P2 = Q2 R2 gives
+  // A1^T = A2 Q2^T with A2 = A1^T Q2 (= P2 R2^T), and A2 P3 = Q3 R3 gives
+  // A2 = Q3 A3^T with A3 = A2^T Q3.  So M = Q Q3 A3^T Q2^T, and the one-sided
+  // Jacobi method on the columns of A3 (A3 J = W Sigma) yields
+  // U = Q Q3 J.  Each step R -> R^T and back is a step of the Cholesky LR
+  // iteration on the column Gram matrix (R^T R -> R R^T): it moves weight to
+  // the diagonal, so the sweeps that follow are fewer (on the move's
+  // 256 x 256 truncation inputs 13 -> 5 sweeps for the row M', 9 -> 6 for a
+  // side product).  The Jacobi input is A3 in column-major order, i.e. the
+  // row-major product Q3^T A2.
+  gemm(c, F64, n, n, m, 1.0, M, n, 1, Q, n, 0, 0.0, A1, n);              // A1 = M^T Q
+  orth_sorted(c, A1, n, n, Q2);
+  gemm(c, F64, n, n, n, 1.0, A1, n, 1, Q2, n, 0, 0.0, A2, n);            // A2 = A1^T Q2
+  orth_sorted(c, A2, n, n, Q3);
+  gemm(c, F64, n, n, n, 1.0, Q3, n, 1, A2, n, 0, 0.0, X, n);             // X = Q3^T A2
   if (cp > n) fill(c, X + (size_t)n * n, F64, (int64_t)(cp - n) * n, 0.0);
   norm2(c, X, (int64_t)n * n, fro);
   if (!c.dry) {
@@ -1071,7 +1098,9 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
     // leaves converged also passes the outer test
     const double tol_in = std::min(32.0, 0.5 * std::max((double)r, 4.0)) * eps;
     const int inner_sweeps = 1;
-    const int max_sweeps = 14;
+    // CTM_DEBUG_MAX_SWEEPS lowers the cap (tests of the non-convergence status)
+    int max_sweeps = 14;
+    if (const char* ms = std::getenv("CTM_DEBUG_MAX_SWEEPS")) max_sweeps = std::max(1, std::min(14, std::atoi(ms)));
     // XCD of this SVD's Jacobi rounds (concurrent SVDs have their buffers
     // megabytes apart, so they mostly land on different XCDs)
     const int xslot = (int)(((uintptr_t)X >> 20) & 7);
@@ -1088,6 +1117,8 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
       }
       hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(1), 0, c.stream, flags);
     }
+    if (c.dev_flags)
+      hipLaunchKernelGGL(jac_converged_check, dim3(1), dim3(1), 0, c.stream, flags, c.dev_flags);
     if (std::getenv("CTM_DEBUG_SWEEPS")) {   // diagnostics only: blocks the host
       int f[3] = {0, 0, 0};
       c.check(hipMemcpyAsync(f, flags, sizeof(f), hipMemcpyDeviceToHost, c.stream));
@@ -1103,7 +1134,8 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
                        c.stream, V, n, sig, order, kk, tau, Uj, S);
     c.check_launch();
   }
-  gemm(c, F64, m, kk, n, 1.0, Q, n, 0, Uj, kk, 0, 0.0, U, kk);          // U = Q J
+  gemm(c, F64, n, kk, n, 1.0, Q3, n, 0, Uj, kk, 0, 0.0, A1, kk);        // Q3 J
+  gemm(c, F64, m, kk, n, 1.0, Q, n, 0, A1, kk, 0, 0.0, U, kk);          // U = Q Q3 J
   sign_fix(c, U, m, kk);
   c.arena.release(mk);
 }

@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void scale_inv_kernel(double* __restrict__ x, 
   const double v = nrm[0];
   const bool bad = !(v > 0.0) || !isfinite(v);
   if (bad) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] = 1;
+    if (blockIdx.x == 0 && threadIdx.x == 0) flags[0] |= 1;
     return;
   }
   const double s = 1.0 / v;
@@ -340,7 +340,7 @@ void* Arena::alloc(size_t bytes) {
   if (top > peak) peak = top;
   if (!dry && top > cap) {
     overflow = true;
-    return nullptr;
+    throw Error(2, "workspace exhausted");
   }
   return (void*)(base + off);
 }

@@ -10,6 +10,13 @@ GPU works on many solves at once; a solve that has converged (delta < tol) or
 reached max_iters is finished with its energy, and its slot and memory are
 freed for the next request.  Latency is arrival -> energy returned.
 
+A request may carry a starting environment (`env`, the 16 named tensors of
+an earlier solve of nearby tensors): the solve then resumes from it instead
+of the traced-boundary start, the reuse of environments across optimisation
+steps that the paper relies on (Sec. V, fast full update; Sec. IV,
+environments "iteratively updated and reused").  With `return_env` the
+final environment comes back with the result, for the next request.
+
 Results do not depend on the mix: each solve runs the same kernels on its own
 data and stream, with fixed reduction orders, so a solve alone and a solve in
 the mix give identical numbers.
@@ -23,7 +30,7 @@ from __future__ import annotations
 
 import time
 from dataclasses import dataclass
-from typing import Dict, List, Optional
+from typing import Any, Dict, List, Optional
 
 
 @dataclass
@@ -37,6 +44,8 @@ class Request:
     max_iters: int = 30
     tol: float = 1e-6
     precision: int = 1          # FP32 chains
+    env: Optional[Dict[str, Any]] = None   # warm start: {name: array} of the 16 tensors
+    return_env: bool = False    # hand the final environment back in Result.env
 
 
 @dataclass
@@ -52,6 +61,7 @@ class Result:
     e_site: Optional[float]
     e_bond: Optional[list]
     status: str = "ok"
+    env: Optional[Dict[str, Any]] = None
 
     @property
     def latency(self) -> float:
@@ -100,6 +110,8 @@ class GpuBackend:
         A, B = self.site_tensors(r.d, r.D, r.seed)
         with torch.cuda.stream(stream):
             s = self.P.Solver(self._cfg(r), A, B, stream=stream)
+            if r.env is not None:
+                s.set_env_dict(r.env)
         s._event = torch.cuda.Event()
         return s
 
@@ -116,6 +128,9 @@ class GpuBackend:
     def finish(self, s):
         e, eb = s.energy()
         return e, eb
+
+    def final_env(self, s):
+        return s.get_env_dict()
 
     def release(self, s):
         stream = s.stream
@@ -172,6 +187,9 @@ class FakeBackend:
 
     def finish(self, h):
         return -0.5, [-0.25] * 4
+
+    def final_env(self, h):
+        return {"iterations": h["k"], "start": h["req"].env}
 
     def release(self, h):
         self.in_use -= self.bytes_of(h["req"])
@@ -241,11 +259,13 @@ class Server:
         return progressed
 
     def _finish(self, a: _Active, status: str = "ok"):
-        e = eb = None
+        e = eb = env = None
         if status == "ok":
             e, eb = self.b.finish(a.handle)
+            if a.req.return_env:
+                env = self.b.final_env(a.handle)
         self.results.append(Result(a.req.id, a.req.D, a.req.chi, a.req.t_arrival, a.t_admit,
-                                   self.b.now(), a.iters, a.delta, e, eb, status))
+                                   self.b.now(), a.iters, a.delta, e, eb, status, env))
         self.b.release(a.handle)
         self.used -= a.nbytes
         self.active.remove(a)

@@ -47,8 +47,9 @@ def gemm(dtype, A, B, ta=False, tb=False, alpha=1.0, beta=0.0, C=None):
     return C
 
 
-def tsvd(M, k, tau=1e-14):
-    """M: numpy float64 (m x n); returns (U, S) numpy via the device kernel."""
+def tsvd(M, k, tau=1e-14, expect=0):
+    """M: numpy float64 (m x n); returns (U, S) numpy via the device kernel
+    (the call's status must equal `expect`)."""
     t = torch()
     m, n = M.shape
     kk = min(k, m, n)
@@ -59,7 +60,7 @@ def tsvd(M, k, tau=1e-14):
     ws = t.empty(nb, dtype=t.uint8, device="cuda")
     st = lib().ctm_kernel_tsvd(dM.data_ptr(), m, n, k, tau, U.data_ptr(), S.data_ptr(),
                                ws.data_ptr(), nb, stream_ptr())
-    assert st == 0, st
+    assert st == expect, st
     t.cuda.synchronize()
     return U.cpu().numpy(), S.cpu().numpy()
 

@@ -46,7 +46,9 @@ def test_workspace_size_validation(lib):
     assert P.workspace_size(good) > 0
     bad = [P.Config(d=1), P.Config(D=0), P.Config(chi=0), P.Config(method=7),
            P.Config(precision=3), P.Config(boot_iters=-1), P.Config(svd_cutoff=-1.0),
-           P.Config(svd_cutoff=1.0)]
+           P.Config(svd_cutoff=1.0),
+           # chi below D^2: the initial traced-boundary bonds would not fit
+           P.Config(D=3, chi=8), P.Config(D=2, chi=3), P.Config(D=8, chi=63)]
     for cfg in bad:
         c = cfg.to_c()
         assert lib.ctm_workspace_size(ctypes.byref(c)) == 0, cfg
@@ -81,6 +83,10 @@ def test_init_rejects_bad_arguments_before_any_device_work(lib):
     assert lib.ctm_init(ctypes.byref(c), A, A, 0, None) == P.CTM_EINVAL
     bad = P.Config(d=2, D=2, chi=0).to_c(0, fake, need)
     assert lib.ctm_init(ctypes.byref(bad), A, A, 0, ctypes.byref(h)) == P.CTM_EINVAL
+    # chi < D^2 is refused before any device work
+    bad = P.Config(d=2, D=2, chi=3).to_c(0, fake, need)
+    assert lib.ctm_init(ctypes.byref(bad), A, A, 0, ctypes.byref(h)) == P.CTM_EINVAL
+    assert P.workspace_size(P.Config(d=2, D=2, chi=4)) > 0
 
 
 def test_null_solver_calls(lib):
@@ -104,6 +110,8 @@ def test_status_strings(lib):
         assert s and s not in seen
         seen.add(s)
     assert "unknown" in P.status_string(99)
+    # a Jacobi SVD that did not converge is reported as a numeric failure
+    assert "SVD" in P.status_string(P.CTM_ENUMERIC)
 
 
 def test_kernel_entry_validation(lib):

@@ -178,3 +178,18 @@ def test_tsvd_tall_compressed_matches_oracle():
     np.testing.assert_allclose(S, So, rtol=0, atol=1e-12 * So[0])
     np.testing.assert_allclose(U.T @ U, np.eye(200), atol=1e-12)
     np.testing.assert_allclose(np.abs(U[:, :20]), np.abs(Uo[:, :20]), atol=1e-10)
+
+
+def test_tsvd_reports_nonconvergence(monkeypatch):
+    """A Jacobi solve still rotating after its last allowed sweep is reported
+    as CTM_ENUMERIC (here with the sweep cap lowered to one through the
+    CTM_DEBUG_MAX_SWEEPS knob; a 200 x 200 Gaussian matrix needs several);
+    with the normal cap the same call succeeds and matches the oracle."""
+    rng = np.random.default_rng(21)
+    M = rng.standard_normal((200, 200))
+    monkeypatch.setenv("CTM_DEBUG_MAX_SWEEPS", "1")
+    tsvd(M, 50, expect=4)
+    monkeypatch.delenv("CTM_DEBUG_MAX_SWEEPS")
+    U, S = tsvd(M, 50)
+    So = np.linalg.svd(M, compute_uv=False)[:50]
+    np.testing.assert_allclose(S, So, rtol=0, atol=1e-12 * So[0])

@@ -1,9 +1,12 @@
-"""Serving on the GPU: every result is the same alone and in the mix."""
+"""Serving on the GPU: every result is the same alone and in the mix, and a
+warm-started request resumes from the environment it carries."""
 
 import numpy as np
 import pytest
 
+import oracle as O
 from gpu_util import log
+from synth import site_tensors
 from paper_2306_08212_amd.serve import GpuBackend, Request, Server, summarize
 
 pytestmark = pytest.mark.gpu
@@ -22,18 +25,67 @@ def _stream(n, seed0=0):
     return out
 
 
-def test_results_identical_alone_and_in_the_mix():
-    reqs = _stream(8)
+def _stream_served(n, seed0=1000):
+    """Requests drawn like the served stream: D uniform in {3..8}, chi
+    uniform in [D^2, min(4 D^2, 256)], FP32 chains; two iterations each (the
+    first is the standard bootstrap) to keep the test short."""
+    rng = np.random.default_rng(7)
+    out = []
+    t = 0.0
+    for i in range(n):
+        D = int(rng.integers(3, 9))
+        chi = int(rng.integers(D * D, min(4 * D * D, 256) + 1))
+        t += float(rng.exponential(0.02))
+        out.append(Request(id=i, d=2, D=D, chi=chi, seed=seed0 + i, t_arrival=t,
+                           max_iters=2, tol=0.0, precision=1))
+    return out
+
+
+@pytest.mark.parametrize("which", ["small", "served"])
+def test_results_identical_alone_and_in_the_mix(which):
+    reqs = _stream(8) if which == "small" else _stream_served(16)
     be = GpuBackend()
-    mixed = Server(be, budget_bytes=8 * 2 ** 30, max_slots=8).run(reqs)
+    budget = (8 if which == "small" else 120) * 2 ** 30
+    mixed = Server(be, budget_bytes=budget, max_slots=8).run(reqs)
     s = summarize(mixed)
     log("mix:", s)
     assert s["solves"] == len(reqs)
     for r in reqs:
-        alone = Server(be, budget_bytes=8 * 2 ** 30, max_slots=1).run(
+        alone = Server(be, budget_bytes=budget, max_slots=1).run(
             [Request(**{**r.__dict__, "t_arrival": 0.0})])[0]
         m = mixed[r.id]
         log(f"req {r.id} D={r.D} chi={r.chi}: alone {alone.e_site!r} mix {m.e_site!r}")
         assert alone.iters == m.iters == r.max_iters
         assert alone.e_site == m.e_site          # bitwise
         assert alone.e_bond == m.e_bond
+
+
+def test_warm_started_request_matches_oracle():
+    """A request carrying an environment (here the oracle's after three
+    iterations, d=2, D=2, chi=8, seed 4) resumes from it: five more FP64
+    iterations served on the GPU match the oracle's solve from the same
+    environment to 1e-10 relative in every energy, and the returned
+    environment's corner spectra match to the oracle's own conditioning
+    (100 times what one-ulp noise in every truncated matrix does to its
+    spectra, never below 1e-10 of sigma_0; as in the FP64 parity tests)."""
+    from test_gpu_parity import _oracle_env_sensitivity, _spectra, _spectra_err
+    A, B = site_tensors(2, 2, 4)
+    env0 = O.solve(A, B, 8, O.REDUCED, max_iters=3)["env"]
+    ref = O.solve(A, B, 8, O.REDUCED, max_iters=5, env=env0)
+    _, _, ssens = _oracle_env_sensitivity(
+        lambda: O.solve(A, B, 8, O.REDUCED, max_iters=5, env=env0)["env"])
+    req = Request(id=0, d=2, D=2, chi=8, seed=4, max_iters=5, tol=0.0, precision=0,
+                  env=env0, return_env=True)
+    res = Server(GpuBackend(), budget_bytes=2 ** 30, max_slots=1).run([req])[0]
+    log(f"warm start: gpu {res.e_site!r} oracle {ref['e_site']!r}")
+    assert res.status == "ok" and res.iters == 5
+    assert abs(res.e_site - ref["e_site"]) <= 1e-10 * abs(ref["e_site"])
+    for g, o in zip(res.e_bond, ref["e_bond"]):
+        assert abs(g - o) <= 1e-10 * abs(ref["e_site"])
+    err = _spectra_err(_spectra(res.env), _spectra(ref["env"]))
+    log(f"warm start: corner spectra error {err:.1e}, oracle sensitivity {ssens:.1e}")
+    assert err < max(1e-10, 100 * ssens)
+    # a cold start of the same request gives a different (earlier) state
+    cold = Server(GpuBackend(), budget_bytes=2 ** 30, max_slots=1).run(
+        [Request(**{**req.__dict__, "env": None})])[0]
+    assert abs(cold.e_site - res.e_site) > 1e-12

@@ -74,3 +74,18 @@ def test_later_arrivals_overlap_running_solves():
     res = Server(be, budget_bytes=100, max_slots=8).run(_reqs(4, gap=0.03))
     first_done = min(r.t_done for r in res)
     assert sum(r.t_admit < first_done for r in res) >= 3
+
+
+def test_warm_start_environment_is_passed_and_returned():
+    """A request's starting environment reaches the backend's solve, and
+    return_env hands the final one back (the FFU-style reuse of
+    environments between optimisation steps)."""
+    be = FakeBackend(10 ** 12, iter_time=lambda r: 0.01, bytes_of=lambda r: 1)
+    reqs = _reqs(3, tol=1e-30, max_iters=4)
+    reqs[1].env = {"C1a": "start-env"}
+    reqs[1].return_env = True
+    reqs[2].return_env = True
+    res = Server(be, budget_bytes=100, max_slots=2).run(reqs)
+    assert res[0].env is None
+    assert res[1].env == {"iterations": 4, "start": {"C1a": "start-env"}}
+    assert res[2].env == {"iterations": 4, "start": None}
