@@ -11,6 +11,7 @@ from .ctm import (  # noqa: F401
     TAU,
     STANDARD,
     REDUCED,
+    REDUCED_ENV,
     double_layer,
     heisenberg_h2,
     truncate,
@@ -20,6 +21,8 @@ from .ctm import (  # noqa: F401
     unframe_env,
     anchor_standard,
     anchor_reduced,
+    anchor_reduced_env,
+    reduced_half_network,
     absorb_chain,
     move,
     ctm_iteration,

@@ -17,6 +17,9 @@ What it computes, and where each part comes from in the paper
                                                      -- Sec. III-IV, Figs. 3-4
 * the row {C'^1, T'^2, C'^2} built with helper isometries {v_l, v_r}
   computed from {C^1, T^1} and {C^2, T^3} alone     -- Appendix, Fig. A
+* reduced-env move: one 4-index isometry from the reduced half-network
+  [C1 T2 C2; T1 z T3] reshaped (chi D^2) x chi, absorbed like the
+  standard one                                       -- Sec. III, Fig. 3(a,b)
 * Heisenberg bond energy                             -- Sec. V, Eq. (1)
 
 Conventions where the paper is silent (its figures are missing), fixed here
@@ -66,8 +69,13 @@ import numpy as np
 
 TAU = 1e-14
 SIGN_TIE = 1e-8
+# LAPACK driver of the SVD in truncate: "gesdd" (divide and conquer, numpy's
+# default) or "gesvd" (QR iteration).  Both are backward-stable SVDs; running
+# the oracle with each measures how far rounding alone moves its results.
+SVD_DRIVER = "gesdd"
 STANDARD = "standard"
 REDUCED = "reduced"
+REDUCED_ENV = "reduced_env"
 
 CORNERS = [f"C{i}{z}" for z in "ab" for i in range(1, 5)]
 ENV_KEYS = [f"{k}{i}{z}" for z in "ab" for k in "CT" for i in range(1, 5)]
@@ -147,7 +155,11 @@ def truncate(M, k, tau=None):
         tau = TAU
     m, n = M.shape
     kk = min(k, m, n)
-    U, S, _ = np.linalg.svd(M, full_matrices=False)
+    if SVD_DRIVER == "gesdd":
+        U, S, _ = np.linalg.svd(M, full_matrices=False)
+    else:
+        import scipy.linalg
+        U, S, _ = scipy.linalg.svd(M, full_matrices=False, lapack_driver=SVD_DRIVER)
     U = np.array(U[:, :kk], dtype=np.float64)
     S = np.array(S[:kk], dtype=np.float64)
     if kk == 0 or not S[0] > 0.0:
@@ -311,13 +323,45 @@ def anchor_reduced(fenv, sites, z, chi, untruncated=False, return_parts=False):
     return v1, v2
 
 
+def reduced_half_network(fenv, sites, z):
+    """The reduced half-network [C1 T2 C2; T1 z T3] of a z-site, open on the
+    bond below it: M[j, kd, bd, j'] (Sec. III: the right half {w, T2_w,
+    C2_w, T3_w} of the half-plaquette is stood in for by {C2_z, T3_z}; the
+    right move's isometry is dropped, since multiplying by a co-isometry
+    from the right leaves the left singular vectors unchanged)."""
+    C1, T1, T2 = fenv[f"C1{z}"], fenv[f"T1{z}"], fenv[f"T2{z}"]
+    C2, T3 = fenv[f"C2{z}"], fenv[f"T3{z}"]
+    a = double_layer(sites[z])
+    L = _c("mi,jklm->iklj", C1, T1)              # L[i, kl, bl, j]
+    R = _c("im,mklj->iklj", C2, T3)              # R[i', kr, br, j']
+    X = _c("iklj,iuvn->kljuvn", L, T2)
+    X = _c("kljuvn,kluvrRdD->jnrRdD", X, a)
+    return _c("jnrRdD,nrRk->jdDk", X, R)
+
+
+def anchor_reduced_env(fenv, sites, z, chi, untruncated=False):
+    """Reduced-env 4-index isometry v_z[j, kd, bd, nu] (Sec. III, Fig.
+    3(a,b)): the top-chi left singular vectors of the reduced half-network
+    reshaped (chi D^2) x chi."""
+    D = sites[z].shape[1]
+    nj = fenv[f"T1{z}"].shape[0]
+    if untruncated:
+        return np.eye(nj * D * D).reshape(nj, D, D, nj * D * D)
+    M = reduced_half_network(fenv, sites, z)
+    nj2 = M.shape[3]
+    U = truncate(M.reshape(nj * D * D, nj2), chi)[0]
+    return U.reshape(nj, D, D, U.shape[1])
+
+
 # ---------------------------------------------------------------- moves
 
-def _new_dims(fenv, z, D, chi):
+def _new_dims(fenv, z, D, chi, method=REDUCED):
     """Bond dimension below a z-site after (standard, reduced) truncation."""
     nj = fenv[f"T1{z}"].shape[0]
     nj2 = fenv[f"T3{z}"].shape[3]
     std = min(chi, nj * D * D, D * D * nj2)
+    if method == REDUCED_ENV:
+        return std, min(chi, nj * D * D, nj2)
     c1 = min(chi, nj * D, D * nj2)
     red = min(chi, c1 * D, nj2)
     return std, red
@@ -330,7 +374,7 @@ def insertion_is_standard(fenv, sites, x, method, chi, untruncated=False):
         return False
     D = sites[x].shape[1]
     for z in (x, _other(x)):
-        std, red = _new_dims(fenv, z, D, chi)
+        std, red = _new_dims(fenv, z, D, chi, method)
         if red < std:
             return True
     return False
@@ -344,10 +388,13 @@ def _insert(fenv, sites, chi, method, untruncated):
     so that all of them sit at the same column.  V_z truncates the bond below
     a z-site (equivalently above the other sublattice)."""
     std = insertion_is_standard(fenv, sites, "a", method, chi, untruncated)
+    four = std or method == REDUCED_ENV      # 4-index isometries
     V = {}
     for z in "ab":
         if std:
             V[z] = anchor_standard(fenv, sites, z, chi, untruncated)
+        elif method == REDUCED_ENV:
+            V[z] = anchor_reduced_env(fenv, sites, z, chi, untruncated)
         else:
             V[z] = anchor_reduced(fenv, sites, z, chi, untruncated)
     new = {}
@@ -361,7 +408,7 @@ def _insert(fenv, sites, chi, method, untruncated):
         # edge left of that y-site: T1_x + site x; top bond V_y, bottom bond V_x
         # corner down-left of that y-site: C4_x T4_x, bond below x (V_x)
         G4 = _c("mj,pkbm->jkbp", C4x, T4x)
-        if std:
+        if four:
             vy, vx = V[y], V[x]
             C1n = _c("jubq,jubn->nq", G, vy)
             Z = _c("pklq,quvn->pkluvn", T1x, vy)
@@ -389,7 +436,8 @@ def move(env, A, B, r, chi, method=REDUCED, untruncated=False):
     """One directional move = the left move in frame r: two column
     insertions (Sec. II), so the left environment advances by one unit cell.
     method=STANDARD forces the standard isometries (used for bootstrap
-    iterations); REDUCED follows the shape rule of the module docstring."""
+    iterations); REDUCED (sequential order) and REDUCED_ENV follow the shape
+    rule of the module docstring."""
     fenv = frame_env(env, r)
     sites = {"a": rotate_site(A, r), "b": rotate_site(B, r)}
     fenv = _insert(fenv, sites, chi, method, untruncated)

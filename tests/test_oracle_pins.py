@@ -22,7 +22,7 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 # ------------------------------------------------------------ closed forms
 
-@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED])
+@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED, O.REDUCED_ENV])
 @pytest.mark.parametrize("chi", [1, 4])
 def test_neel_product_state_energy(method, chi):
     """D = 1 Neel state: <S.S> = -1/4 on every bond, -1/2 per site."""
@@ -47,7 +47,7 @@ def test_random_product_state_energy(seed):
     real states)."""
     A, B, pa, pb = product_state_tensors(2, seed)
     exact = _spin_expectation(pa) @ _spin_expectation(pb)
-    for method in (O.STANDARD, O.REDUCED):
+    for method in (O.STANDARD, O.REDUCED, O.REDUCED_ENV):
         r = O.solve(A, B, 3, method, max_iters=2)
         for e in r["e_bond"]:
             assert abs(e - exact) < 1e-13
@@ -182,7 +182,7 @@ def _ctm_all(env, A, B, h2):
             O.bond_energy(env, A, B, "a", h2, 1), O.bond_energy(env, A, B, "b", h2, 1)]
 
 
-@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED])
+@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED, O.REDUCED_ENV])
 def test_untruncated_ctm_equals_bruteforce_patch(method):
     """With identity isometries every move is an exact contraction: after
     moves L / L,R,U,D the environment is the traced boundary of a finite
@@ -251,7 +251,7 @@ def test_onsager_golden_values():
 
 
 @pytest.mark.parametrize("beta", [0.3, 0.4])
-@pytest.mark.parametrize("method,boot", [(O.STANDARD, 1), (O.REDUCED, 3)])
+@pytest.mark.parametrize("method,boot", [(O.STANDARD, 1), (O.REDUCED, 3), (O.REDUCED_ENV, 3)])
 def test_onsager_nearest_neighbour(beta, method, boot):
     """Converged truncated CTMRG (projectors and SVDs included) reproduces
     Onsager's exact nearest-neighbour correlation.  The Ising legs span a
@@ -335,7 +335,7 @@ def _gauge(A, B, seed):
     return A2, B2
 
 
-@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED])
+@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED, O.REDUCED_ENV])
 @pytest.mark.parametrize("D,chi,its", [(2, 8, 20), (3, 18, 3)])
 def test_bond_gauge_invariance(method, D, chi, its):
     """An independent real orthogonal change of basis on each of the four
@@ -357,7 +357,7 @@ def test_broken_gauge_changes_energy():
     assert abs(e1 - e2) > 1e-3
 
 
-@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED])
+@pytest.mark.parametrize("method", [O.STANDARD, O.REDUCED, O.REDUCED_ENV])
 def test_spin_rotation_invariance(method):
     """A real rotation of the physical index of A and B is a global SU(2)
     rotation: S.S energies and the norm network (corner spectra) are
@@ -423,6 +423,49 @@ def test_reduced_row_is_exact_without_truncation():
                           env[f"C1{z}"], env[f"T1{z}"], env[f"T2{z}"], X, X,
                           env[f"C2{z}"], env[f"T3{z}"], optimize=True)
         np.testing.assert_allclose(parts["Mp"], exact, rtol=0, atol=1e-12 * np.abs(exact).max())
+
+
+def test_reduced_env_network_and_rank():
+    """The reduced-env sub-network (Sec. III) is [C1 T2 C2; T1 z T3]
+    contracted as one network (written out independently here, ket and bra
+    sites instead of the double layer), and its isometry spans that
+    network's column space: rank at most the far bond T3.q, and v v^T M = M
+    when chi covers the rank."""
+    A, B = site_tensors(2, 2, 8)
+    env = O.solve(A, B, 8, O.STANDARD, max_iters=2)["env"]
+    sites = {"a": A, "b": B}
+    for z in "ab":
+        X = sites[z]
+        exact = np.einsum("mi,jklm,iuvq,skurd,slvRD,qn,nrRo->jdDo",
+                          env[f"C1{z}"], env[f"T1{z}"], env[f"T2{z}"], X, X,
+                          env[f"C2{z}"], env[f"T3{z}"], optimize=True)
+        M = OC.reduced_half_network(env, sites, z)
+        np.testing.assert_allclose(M, exact, rtol=0, atol=1e-13 * np.abs(exact).max())
+        nj, D, _, nj2 = M.shape
+        v = OC.anchor_reduced_env(env, sites, z, 8)
+        assert v.shape == (nj, D, D, min(8, nj2))
+        V = v.reshape(nj * D * D, -1)
+        Mm = M.reshape(nj * D * D, nj2)
+        np.testing.assert_allclose(V @ (V.T @ Mm), Mm, rtol=0, atol=1e-12 * np.abs(Mm).max())
+
+
+def test_reduced_env_and_sequential_projectors_agree_without_first_stage_cut():
+    """With nothing cut before the last stage (v_l, v_r and v^1 keep their
+    full range, as from the traced-boundary start at D=2, chi=16), the
+    sequential-order isometry v = (v^1 x 1) v^2 spans the same subspace as
+    the reduced-env one: both are the column space of the same reduced
+    half-network (Secs. III-IV)."""
+    A, B = site_tensors(2, 2, 5)
+    env = O.init_env(A, B)
+    sites = {"a": A, "b": B}
+    for z in "ab":
+        v1, v2 = OC.anchor_reduced(env, sites, z, 16)
+        nj, D, c1 = v1.shape
+        assert c1 == nj * D
+        vs = np.einsum("jdm,mbn->jdbn", v1, v2).reshape(nj * D * D, -1)
+        ve = OC.anchor_reduced_env(env, sites, z, 16).reshape(nj * D * D, -1)
+        assert vs.shape == ve.shape
+        np.testing.assert_allclose(vs @ vs.T, ve @ ve.T, rtol=0, atol=1e-12)
 
 
 def test_sequential_isometries_reproduce_first_stage():
