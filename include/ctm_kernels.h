@@ -41,6 +41,23 @@ int ctm_kernel_tsvd(const double *M, int m, int n, int k, double tau, double *U,
                     void *workspace, size_t workspace_bytes, void *stream);
 size_t ctm_kernel_tsvd_workspace(int m, int n, int k);
 
+/* Allocation-free variant of ctm_kernel_tsvd, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and statuses as
+ * ctm_kernel_tsvd, bitwise, but the workspace is a fixed device array inside
+ * the library, one copy per GPU (its address is looked up on the first call
+ * on each device), of ctm_kernel_tsvd_static_max() bytes (64 MiB: every
+ * truncation of the move up to d=2, D=8, chi=256, e.g. 2048 x 2048 to 256,
+ * fits).  Calls no hipMalloc or hipFree.  CTM_ENOMEM when
+ * ctm_kernel_tsvd_workspace(m, n, k) exceeds that size.  Every call on one
+ * GPU shares that GPU's array and overwrites it (the error word it needs is
+ * cleared by each call): calls that overlap on one GPU -- on different
+ * streams or from different host threads -- race and must not be issued.
+ * Synchronises the stream at the end, as ctm_kernel_tsvd does. */
+int ctm_kernel_tsvd_static(const double *M, int m, int n, int k, double tau, double *U, double *S,
+                           void *stream);
+size_t ctm_kernel_tsvd_static_max(void);
+
 /* Index permute between contractions: out[i_0..] = scale * in[...] with out
  * dimension j equal to input dimension perm[j]; nd <= 8; dims are the input
  * dimensions (host array).  dt_in / dt_out as for ctm_kernel_gemm (2 = BF16)

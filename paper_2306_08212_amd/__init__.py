@@ -30,7 +30,7 @@ EXPORTS = ["ctm_workspace_size", "ctm_init", "ctm_move", "ctm_iterate", "ctm_con
            "ctm_iterate_delta", "ctm_read_delta", "ctm_energy", "ctm_get_env", "ctm_set_env", "ctm_moves_done", "ctm_set_precision", "ctm_set_graphs",
            "ctm_profile", "ctm_profile_read", "ctm_destroy",
            "ctm_status_string", "ctm_kernel_gemm", "ctm_kernel_tsvd", "ctm_kernel_tsvd_workspace",
-           "ctm_kernel_permute"]
+           "ctm_kernel_permute", "ctm_kernel_tsvd_static", "ctm_kernel_tsvd_static_max"]
 
 
 class CtmConfig(ctypes.Structure):
@@ -107,6 +107,10 @@ def load(path: str = LIB_PATH):
     lib.ctm_kernel_tsvd.restype = I
     lib.ctm_kernel_tsvd_workspace.argtypes = [I, I, I]
     lib.ctm_kernel_tsvd_workspace.restype = ctypes.c_size_t
+    lib.ctm_kernel_tsvd_static.argtypes = [P, I, I, I, D, P, P, P]
+    lib.ctm_kernel_tsvd_static.restype = I
+    lib.ctm_kernel_tsvd_static_max.argtypes = []
+    lib.ctm_kernel_tsvd_static_max.restype = ctypes.c_size_t
     lib.ctm_kernel_permute.argtypes = [I, P, I, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(I), I, P, D, P]
     lib.ctm_kernel_permute.restype = I

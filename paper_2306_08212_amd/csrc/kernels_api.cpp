@@ -3,7 +3,42 @@
 #include "../../include/ctm_kernels.h"
 #include "ctm_internal.h"
 
+#include <mutex>
+
 using namespace ctm;
+
+// Device-resident scratch of the allocation-free truncation
+// (ctm_kernel_tsvd_static): one copy per GPU, held until the process ends.
+// Host code never uses the symbol's name as an address: the device address
+// is looked up once per device with hipGetSymbolAddress and kept below.
+static constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current device's scratch (looked up on the first call on
+// that device, with that device current), or nullptr on a HIP error.
+void* scratch_of_current_device(hipError_t* err) {
+  int dev = -1;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  if (dev < 0 || dev >= kMaxDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
 
 extern "C" {
 
@@ -44,6 +79,34 @@ int ctm_kernel_tsvd(const double* M, int m, int n, int k, double tau, double* U,
   c.stream = (hipStream_t)stream;
   c.arena.base = (char*)workspace;
   c.arena.cap = workspace_bytes;
+  try {
+    tsvd_flagged(c, M, m, n, k, tau, U, S);
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return c.hip_err == hipSuccess ? CTM_EINVAL : CTM_EHIP;
+  }
+  int flag = 0;
+  c.check(hipMemcpyAsync(&flag, c.dev_flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  c.check(hipStreamSynchronize(c.stream));
+  if (c.hip_err != hipSuccess) return CTM_EHIP;
+  return flag ? CTM_ENUMERIC : CTM_OK;
+}
+
+size_t ctm_kernel_tsvd_static_max(void) { return kStaticScratchBytes; }
+
+int ctm_kernel_tsvd_static(const double* M, int m, int n, int k, double tau, double* U, double* S,
+                           void* stream) {
+  if (!M || !U || !S || m < 1 || n < 1 || k < 1 || !(tau >= 0.0)) return CTM_EINVAL;
+  const size_t need = ctm_kernel_tsvd_workspace(m, n, k);
+  if (need == 0 || need > kStaticScratchBytes) return CTM_ENOMEM;
+  hipError_t err = hipSuccess;
+  void* ws = scratch_of_current_device(&err);
+  if (ws == nullptr) return CTM_EHIP;
+  Ctx c;
+  c.stream = (hipStream_t)stream;
+  c.arena.base = (char*)ws;
+  c.arena.cap = kStaticScratchBytes;
   try {
     tsvd_flagged(c, M, m, n, k, tau, U, S);
   } catch (const Error& e) {
