@@ -29,6 +29,10 @@ from .ctm import (  # noqa: F401
     corner_spectra,
     bond_energy,
     energy,
+    site_rdm,
+    expect1,
+    staggered_magnetisation,
+    row_correlation,
     solve,
     CORNERS,
     ENV_KEYS,

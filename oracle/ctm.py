@@ -242,13 +242,14 @@ def anchor_standard(fenv, sites, z, chi, untruncated=False):
     return U.reshape(nj, D, D, U.shape[1])
 
 
-def _split_iso(X, chi, untruncated):
+def _split_iso(X, chi, untruncated, chi1=None):
     """Two-stage isometry of a 4-index X[i, k, b, j] bonded on (i, k, b):
-    v1 from X as [(i,k),(b,j)], then v2 from X' = v1^T X as [(mu,b), j];
-    returns (v1[i,k,mu], v2[mu,b,nu], X''[nu, j]) (Appendix, Fig. A(c) for
-    {C^1,T^1} and {C^2,T^3}; Sec. IV for the row {C'^1,T'^2,C'^2})."""
+    v1 from X as [(i,k),(b,j)] (top chi1, default chi), then v2 from
+    X' = v1^T X as [(mu,b), j] (top chi); returns (v1[i,k,mu], v2[mu,b,nu],
+    X''[nu, j]) (Appendix, Fig. A(c) for {C^1,T^1} and {C^2,T^3}; Sec. IV for
+    the row {C'^1,T'^2,C'^2})."""
     ni, D, _, nj = X.shape
-    v1 = _iso(X.reshape(ni * D, D * nj), chi, untruncated)
+    v1 = _iso(X.reshape(ni * D, D * nj), chi if chi1 is None else chi1, untruncated)
     c1 = v1.shape[1]
     v1 = v1.reshape(ni, D, c1)
     Xp = _c("ikm,iklj->mlj", v1, X)
@@ -284,7 +285,8 @@ def _site_in_T2(A):
     return np.ascontiguousarray(A.transpose(0, 2, 1, 4, 3))
 
 
-def anchor_reduced(fenv, sites, z, chi, untruncated=False, return_parts=False):
+def anchor_reduced(fenv, sites, z, chi, untruncated=False, return_parts=False, chi_p=None,
+                   chi_pp=None):
     """Split isometries (v^1_z[j,kd,mu], v^2_z[mu,bd,nu]) for the bond below
     a z-site in the left column, from the reduced half-network
     [C1 T2 C2; T1 z T3] of z alone (Sec. III: the right half is replaced by
@@ -292,7 +294,11 @@ def anchor_reduced(fenv, sites, z, chi, untruncated=False, return_parts=False):
     C'^2}; Appendix: that row is built with {v_l, v_r} from {C^1, T^1} and
     {C^2, T^3}).  M' is reshaped (chi D) x (D chi) with the ket leg paired
     with the left boundary bond (Sec. IV), then N = v1^T M' as (chi' D) x chi.
+    chi_p (chi', Sec. IV) bounds v^1 and chi_pp (chi'', Sec. V) the first
+    stage of the helper isometries; both default to chi (the paper's runs).
     """
+    chi_p = chi if chi_p is None else chi_p
+    chi_pp = chi if chi_pp is None else chi_pp
     C1, T1, T2 = fenv[f"C1{z}"], fenv[f"T1{z}"], fenv[f"T2{z}"]
     C2, T3 = fenv[f"C2{z}"], fenv[f"T3{z}"]
     D = sites[z].shape[1]
@@ -303,14 +309,14 @@ def anchor_reduced(fenv, sites, z, chi, untruncated=False, return_parts=False):
         return v1, v2
     # left part: L[i,kl,bl,j] = C1[m,i] T1[j,kl,bl,m]
     L = _c("mi,jklm->iklj", C1, T1)
-    vl1, vl2, Cp1 = _split_iso(L, chi, False)
+    vl1, vl2, Cp1 = _split_iso(L, chi, False, chi_pp)
     # right part: R[i,kr,br,j] = C2[i,m] T3[m,kr,br,j]
     R = _c("im,mklj->iklj", C2, T3)
-    vr1, vr2, Cp2 = _split_iso(R, chi, False)
+    vr1, vr2, Cp2 = _split_iso(R, chi, False, chi_pp)
     Tp2 = absorb_chain(T2, _site_in_T2(sites[z]), vl1, vl2, vr1, vr2)
     Mp = _c("nj,ndDo->jdDo", Cp1, Tp2)
     Mp = _c("jdDo,ok->jdDk", Mp, Cp2)
-    v1 = truncate(Mp.reshape(nj * D, D * nj2), chi)[0]
+    v1 = truncate(Mp.reshape(nj * D, D * nj2), chi_p)[0]
     c1 = v1.shape[1]
     v1 = v1.reshape(nj, D, c1)
     N = _c("jdm,jdDk->mDk", v1, Mp)
@@ -355,39 +361,40 @@ def anchor_reduced_env(fenv, sites, z, chi, untruncated=False):
 
 # ---------------------------------------------------------------- moves
 
-def _new_dims(fenv, z, D, chi, method=REDUCED):
+def _new_dims(fenv, z, D, chi, method=REDUCED, chi_p=None):
     """Bond dimension below a z-site after (standard, reduced) truncation."""
+    chi_p = chi if chi_p is None else chi_p
     nj = fenv[f"T1{z}"].shape[0]
     nj2 = fenv[f"T3{z}"].shape[3]
     std = min(chi, nj * D * D, D * D * nj2)
     if method == REDUCED_ENV:
         return std, min(chi, nj * D * D, nj2)
-    c1 = min(chi, nj * D, D * nj2)
+    c1 = min(chi_p, nj * D, D * nj2)
     red = min(chi, c1 * D, nj2)
     return std, red
 
 
-def insertion_is_standard(fenv, sites, x, method, chi, untruncated=False):
+def insertion_is_standard(fenv, sites, x, method, chi, untruncated=False, chi_p=None):
     if method == STANDARD:
         return True
     if untruncated:
         return False
     D = sites[x].shape[1]
     for z in (x, _other(x)):
-        std, red = _new_dims(fenv, z, D, chi, method)
+        std, red = _new_dims(fenv, z, D, chi, method, chi_p)
         if red < std:
             return True
     return False
 
 
-def _insert(fenv, sites, chi, method, untruncated):
+def _insert(fenv, sites, chi, method, untruncated, chi_p=None, chi_pp=None):
     """Insert one column into the left environment and truncate the enlarged
     bonds (Sec. II, Fig. 2(a,b)).  Reading: the column is {T2, site, site,
     T4} with both sublattices in turn down the column; every tensor of the
     left column (C1, T1, C4 of both sublattices) moves one site to the right
     so that all of them sit at the same column.  V_z truncates the bond below
     a z-site (equivalently above the other sublattice)."""
-    std = insertion_is_standard(fenv, sites, "a", method, chi, untruncated)
+    std = insertion_is_standard(fenv, sites, "a", method, chi, untruncated, chi_p)
     four = std or method == REDUCED_ENV      # 4-index isometries
     V = {}
     for z in "ab":
@@ -396,7 +403,7 @@ def _insert(fenv, sites, chi, method, untruncated):
         elif method == REDUCED_ENV:
             V[z] = anchor_reduced_env(fenv, sites, z, chi, untruncated)
         else:
-            V[z] = anchor_reduced(fenv, sites, z, chi, untruncated)
+            V[z] = anchor_reduced(fenv, sites, z, chi, untruncated, chi_p=chi_p, chi_pp=chi_pp)
     new = {}
     for x in "ab":
         y = _other(x)
@@ -432,7 +439,7 @@ def _insert(fenv, sites, chi, method, untruncated):
     return out
 
 
-def move(env, A, B, r, chi, method=REDUCED, untruncated=False):
+def move(env, A, B, r, chi, method=REDUCED, untruncated=False, chi_p=None, chi_pp=None):
     """One directional move = the left move in frame r: two column
     insertions (Sec. II), so the left environment advances by one unit cell.
     method=STANDARD forces the standard isometries (used for bootstrap
@@ -440,17 +447,17 @@ def move(env, A, B, r, chi, method=REDUCED, untruncated=False):
     rule of the module docstring."""
     fenv = frame_env(env, r)
     sites = {"a": rotate_site(A, r), "b": rotate_site(B, r)}
-    fenv = _insert(fenv, sites, chi, method, untruncated)
-    fenv = _insert(fenv, sites, chi, method, untruncated)
+    fenv = _insert(fenv, sites, chi, method, untruncated, chi_p, chi_pp)
+    fenv = _insert(fenv, sites, chi, method, untruncated, chi_p, chi_pp)
     return unframe_env(fenv, r)
 
 
 MOVE_ORDER = (0, 2, 1, 3)   # left, right, up, down (Sec. II)
 
 
-def ctm_iteration(env, A, B, chi, method=REDUCED, untruncated=False):
+def ctm_iteration(env, A, B, chi, method=REDUCED, untruncated=False, chi_p=None, chi_pp=None):
     for r in MOVE_ORDER:
-        env = move(env, A, B, r, chi, method, untruncated)
+        env = move(env, A, B, r, chi, method, untruncated, chi_p, chi_pp)
     return env
 
 
@@ -510,10 +517,102 @@ def energy(env, A, B, h2=None):
     return 0.5 * sum(eb), eb
 
 
+# ---------------------------------------------------------------- observables
+
+def site_rdm(env, A, B, z):
+    """One-site reduced density matrix rho[s, S] of a z-site (ket index s,
+    bra index S), unnormalised: the site between its four corners and four
+    edges (3 x 3 network, frame 0).  <O>_z = sum rho[s, S] O[S, s] / tr rho
+    gives the order parameters of Sec. V (staggered magnetisation, m_z) and
+    the transverse-field term of the Ising model."""
+    X = A if z == "a" else B
+    e = {k: env[f"{k}{z}"] for k in ("C1", "C2", "C3", "C4", "T1", "T2", "T3", "T4")}
+    # left column C1 T1 C4 with the top and bottom edges, then the site
+    # (ket, bra) and the right column C2 T3 C3, one pair at a time
+    L = _c("ha,ilLh->ailL", e["C1"], e["T1"])
+    L = _c("ailL,gi->algL", L, e["C4"])
+    L = _c("algL,auUb->lgLuUb", L, e["T2"])
+    L = _c("lgLuUb,fdDg->lLuUbfdD", L, e["T4"])
+    L = _c("lLuUbfdD,slurd->LUbfDsr", L, X)
+    L = _c("LUbfDsr,SLURD->bfsrSR", L, X)
+    R = _c("bc,crRe->brRe", e["C2"], e["T3"])
+    R = _c("brRe,ef->brRf", R, e["C3"])
+    return _c("bfsrSR,brRf->sS", L, R)
+
+
+def expect1(env, A, B, op):
+    """(<op>_a, <op>_b) for a d x d one-site operator op[s', s]."""
+    out = []
+    for z in "ab":
+        rho = site_rdm(env, A, B, z)
+        out.append(float(_c("sS,Ss->", rho, op) / np.trace(rho)))
+    return out
+
+
+def staggered_magnetisation(env, A, B):
+    """m_s = |<S>_a - <S>_b| / 2 with S = sigma / 2 (Sec. V); for real
+    tensors <S^y> = 0, so only S^x and S^z enter."""
+    sx = np.array([[0.0, 0.5], [0.5, 0.0]])
+    sz = np.array([[0.5, 0.0], [0.0, -0.5]])
+    xa, xb = expect1(env, A, B, sx)
+    za, zb = expect1(env, A, B, sz)
+    return 0.5 * float(np.hypot(xa - xb, za - zb))
+
+
+def row_correlation(env, A, B, op, L):
+    """C(x) = <op_0 op_x> - <op_0><op_x> for x = 1..L along a row (frame 0),
+    site 0 on sublattice a (Sec. V, Fig. 8(b): S_zz(x)).  The row between
+    the edges above (T2) and below (T4) is contracted column by column from
+    the left boundary {C1, T1, C4} of site 0 to the right boundary
+    {C2, T3, C3} of site x."""
+    sites = {"a": A, "b": B}
+
+    def left(z, o):
+        # left boundary + site z with o on its physical legs -> V[c, r, R, f]
+        X = sites[z]
+        L = _c("ha,ilLh->ailL", env[f"C1{z}"], env[f"T1{z}"])
+        L = _c("ailL,gi->algL", L, env[f"C4{z}"])
+        L = _c("algL,auUc->lgLuUc", L, env[f"T2{z}"])
+        L = _c("lgLuUc,fdDg->lLuUcfdD", L, env[f"T4{z}"])
+        L = _c("lLuUcfdD,slurd->LUcfDsr", L, X)
+        L = _c("LUcfDsr,Ss->LUcfDSr", L, o)
+        return _c("LUcfDSr,SLURD->crRf", L, X)
+
+    def column(V, z, o):
+        # absorb the column {T2_z, z, T4_z} with o on the site: V[c, r, R, f]
+        X = sites[z]
+        W = _c("crRf,cuUb->rRfuUb", V, env[f"T2{z}"])
+        W = _c("rRfuUb,srutd->RfUbstd", W, X)
+        W = _c("RfUbstd,Ss->RfUbStd", W, o)
+        W = _c("RfUbStd,SRUTD->fbtdTD", W, X)
+        return _c("fbtdTD,gdDf->btTg", W, env[f"T4{z}"])
+
+    def right(V, z, o):
+        # close with site z (op o) and its right boundary {C2, T3, C3}
+        W = column(V, z, o)                                  # [b, t, T, g]
+        R = _c("bn,ntTe->btTe", env[f"C2{z}"], env[f"T3{z}"])
+        R = _c("btTe,eg->btTg", R, env[f"C3{z}"])
+        return float(_c("btTg,btTg->", W, R))
+
+    d = A.shape[0]
+    one = np.eye(d)
+    VO, VI = left("a", op), left("a", one)
+    out = []
+    for x in range(1, L + 1):
+        z = "a" if x % 2 == 0 else "b"
+        oo, io = right(VO, z, op), right(VI, z, op)
+        oi, ii = right(VO, z, one), right(VI, z, one)
+        out.append(oo / ii - (oi / ii) * (io / ii))
+        VO, VI = column(VO, z, one), column(VI, z, one)
+        nrm = np.linalg.norm(VI)
+        VO, VI = VO / nrm, VI / nrm
+    return out
+
+
 # ---------------------------------------------------------------- driver
 
 def solve(A, B, chi, method=REDUCED, max_iters=20, tol=0.0, h2=None, env=None,
-          boot_iters=0, callback=None):
+          boot_iters=0, callback=None, chi_p=None, chi_pp=None):
     """Iterate CTM until the corner-spectrum change delta < tol (or
     max_iters).  The first boot_iters iterations use the standard move
     whatever the method.  Returns dict(env, iters, delta, e_site, e_bond,
@@ -526,7 +625,7 @@ def solve(A, B, chi, method=REDUCED, max_iters=20, tol=0.0, h2=None, env=None,
     delta = np.inf
     while it < max_iters:
         m = STANDARD if it < boot_iters else method
-        env = ctm_iteration(env, A, B, chi, m)
+        env = ctm_iteration(env, A, B, chi, m, chi_p=chi_p, chi_pp=chi_pp)
         it += 1
         cur = corner_spectra(env, chi)
         delta = max(float(np.max(np.abs(cur[k] - prev[k]))) for k in CORNERS)

@@ -225,6 +225,22 @@ def _onsager_nn(beta):
                                       * ellipk(k * k))
 
 
+_ISING_CACHE = {}
+
+
+def _ising_solve(beta, method, boot):
+    """Converged CTMRG of the classical Ising PEPS at beta (chi = 24, delta
+    < 1e-11), with the nearest-neighbour sigma^z sigma^z as bond operator;
+    cached, since several pins use the same solve."""
+    key = (beta, method, boot)
+    if key not in _ISING_CACHE:
+        A = _ising_peps(beta)
+        zz = np.kron(np.diag([1.0, -1.0]), np.diag([1.0, -1.0]))
+        _ISING_CACHE[key] = O.solve(A, A, 24, method, max_iters=60, tol=1e-11, h2=zz,
+                                    boot_iters=boot)
+    return _ISING_CACHE[key]
+
+
 def _ising_peps(beta):
     """A[s,l,u,r,d] = Q[s,l]Q[s,u]Q[s,r]Q[s,d], Q Q^T = exp(beta/2 s s'):
     then <psi|psi> is the classical Ising partition function at beta and
@@ -250,16 +266,14 @@ def test_onsager_golden_values():
         assert abs(_onsager_nn(beta) - v) < 1e-11
 
 
-@pytest.mark.parametrize("beta", [0.3, 0.4])
-@pytest.mark.parametrize("method,boot", [(O.STANDARD, 1), (O.REDUCED, 3), (O.REDUCED_ENV, 3)])
+@pytest.mark.parametrize("beta,method,boot", [(0.3, O.STANDARD, 1), (0.3, O.REDUCED, 3),
+                                              (0.3, O.REDUCED_ENV, 3), (0.4, O.STANDARD, 1)])
 def test_onsager_nearest_neighbour(beta, method, boot):
     """Converged truncated CTMRG (projectors and SVDs included) reproduces
     Onsager's exact nearest-neighbour correlation.  The Ising legs span a
     2-dim subspace of each D^2 bond, so the reduced move needs a few
     standard iterations to reach full numerical rank before it takes over."""
-    A = _ising_peps(beta)
-    zz = np.kron(np.diag([1.0, -1.0]), np.diag([1.0, -1.0]))
-    r = O.solve(A, A, 24, method, max_iters=60, tol=1e-11, h2=zz, boot_iters=boot)
+    r = _ising_solve(beta, method, boot)
     exact = _golden_onsager()[beta]
     for e in r["e_bond"]:
         assert abs(e - exact) < 1e-9
@@ -487,15 +501,16 @@ def test_sequential_isometries_reproduce_first_stage():
         np.testing.assert_allclose(v.T @ v, np.diag((np.abs(v).sum(0) > 0).astype(float)), atol=1e-12)
 
 
-@pytest.mark.parametrize("D,chis", [(2, (8, 32)), (3, (9, 27))])
-def test_reduced_approaches_standard_as_chi_grows(D, chis):
+@pytest.mark.parametrize("method", [O.REDUCED, O.REDUCED_ENV])
+def test_reduced_approaches_standard_as_chi_grows(method):
     """Trend only (Sec. V: the methods agree for large chi); the finite-chi
-    gap itself is not pinned."""
-    A, B = site_tensors(2, D, 0)
+    gap itself is not pinned.  D=2, chi = 4 and 16 (the largest bond the
+    traced boundary can reach at D=2 is D^4 = 16)."""
+    A, B = site_tensors(2, 2, 0)
     gaps = []
-    for chi in chis:
-        es = O.solve(A, B, chi, O.STANDARD, max_iters=30, tol=1e-10)["e_site"]
-        er = O.solve(A, B, chi, O.REDUCED, max_iters=30, tol=1e-10)["e_site"]
+    for chi in (4, 16):
+        es = O.solve(A, B, chi, O.STANDARD, max_iters=20, tol=1e-10)["e_site"]
+        er = O.solve(A, B, chi, method, max_iters=20, tol=1e-10)["e_site"]
         gaps.append(abs(es - er))
     assert gaps[1] < gaps[0] / 10
 
@@ -550,3 +565,95 @@ def test_left_move_changes_only_the_left_column():
                 for z in "ab"}
         assert changed <= left and changed, (r, sorted(changed))
         env = new
+
+
+# ------------------------------------------------------------ observables
+
+SX = np.array([[0.0, 0.5], [0.5, 0.0]])
+SZ = np.array([[0.5, 0.0], [0.0, -0.5]])
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_product_state_one_site_values_and_no_correlation(seed):
+    """D = 1 product states: <O>_z = psi^T O psi / psi^T psi exactly, and
+    every connected correlation along a row vanishes."""
+    A, B, pa, pb = product_state_tensors(2, seed)
+    env = O.solve(A, B, 3, O.REDUCED, max_iters=2)["env"]
+    for op in (SX, SZ):
+        got = O.expect1(env, A, B, op)
+        assert abs(got[0] - pa @ op @ pa / (pa @ pa)) < 1e-14
+        assert abs(got[1] - pb @ op @ pb / (pb @ pb)) < 1e-14
+    c = O.row_correlation(env, A, B, SZ, 5)
+    assert np.abs(c).max() < 1e-14
+
+
+def test_neel_staggered_magnetisation():
+    A = np.zeros((2, 1, 1, 1, 1)); A[0] = 1.0
+    B = np.zeros((2, 1, 1, 1, 1)); B[1] = 1.0
+    env = O.solve(A, B, 2, O.STANDARD, max_iters=2)["env"]
+    assert abs(O.staggered_magnetisation(env, A, B) - 0.5) < 1e-15
+
+
+def test_nearest_correlation_equals_bond_network():
+    """C(1) from the row contraction equals <O O> from the (independently
+    written) bond energy network minus <O>_a <O>_b, on a generic state."""
+    A, B = site_tensors(2, 2, 6)
+    env = O.solve(A, B, 8, O.REDUCED, max_iters=6)["env"]
+    c1 = O.row_correlation(env, A, B, SZ, 1)[0]
+    one = np.eye(2)
+    za = O.bond_energy(env, A, B, "a", np.kron(SZ, one), 0)
+    zb = O.bond_energy(env, A, B, "a", np.kron(one, SZ), 0)
+    zz = O.bond_energy(env, A, B, "a", np.kron(SZ, SZ), 0)
+    assert abs(c1 - (zz - za * zb)) < 1e-13
+
+
+def test_ising_row_correlation_onsager_and_decay():
+    """Classical Ising PEPS at beta = 0.3 (disordered, <sigma^z> = 0): the
+    row correlation of sigma^z at distance 1 is Onsager's nearest-neighbour
+    value, and it decays with distance (finite correlation length)."""
+    A = _ising_peps(0.3)
+    sz = np.diag([1.0, -1.0])
+    env = _ising_solve(0.3, O.STANDARD, 1)["env"]
+    m = O.expect1(env, A, A, sz)
+    assert abs(m[0]) < 1e-10 and abs(m[1]) < 1e-10
+    c = O.row_correlation(env, A, A, sz, 8)
+    assert abs(c[0] - _golden_onsager()[0.3]) < 1e-9
+    assert all(c[i + 1] < c[i] for i in range(7)) and c[7] > 0
+    # geometric decay: the ratio of successive values settles
+    ratios = [c[i + 1] / c[i] for i in range(3, 7)]
+    assert max(ratios) - min(ratios) < 0.05
+
+
+# ------------------------------------------------------------ chi' and chi''
+
+def test_chi_p_and_chi_pp_reach_the_right_stages():
+    """chi' bounds the anchors' first stage v^1 (Sec. IV) and chi'' the
+    helper isometries' first stage (App.).  With both large enough that no
+    first stage cuts (here 16 = chi D at D=2, chi=8), the sequential-order
+    isometry spans the column space of the exact reduced half-network M,
+    like the reduced-env one: P M = M to rounding (the directions of M with
+    singular values near 1e-12 are themselves fixed only to eps / gap, so
+    the projectors are compared on M).  With chi' = chi (the default) v^1
+    cuts and P M misses M by far more.  Shapes follow chi', chi''."""
+    A, B = site_tensors(2, 2, 4)
+    env = O.solve(A, B, 8, O.STANDARD, max_iters=2)["env"]
+    sites = {"a": A, "b": B}
+    for z in "ab":
+        M = OC.reduced_half_network(env, sites, z)
+        nj, D, _, nj2 = M.shape
+        Mm = M.reshape(nj * D * D, nj2)
+        nrm = np.linalg.norm(Mm)
+        v1, v2, parts = OC.anchor_reduced(env, sites, z, 8, chi_p=16, chi_pp=16, return_parts=True)
+        assert v1.shape == (nj, D, 16) and parts["vl1"].shape[2] == 16
+        vs = np.einsum("jdm,mbn->jdbn", v1, v2).reshape(nj * D * D, -1)
+        assert np.linalg.norm(vs @ (vs.T @ Mm) - Mm) < 1e-13 * nrm
+        ve = OC.anchor_reduced_env(env, sites, z, 8).reshape(nj * D * D, -1)
+        assert np.linalg.norm(ve @ (ve.T @ Mm) - Mm) < 1e-13 * nrm
+        v1d, v2d = OC.anchor_reduced(env, sites, z, 8)
+        assert v1d.shape == (nj, D, 8)
+        vd = np.einsum("jdm,mbn->jdbn", v1d, v2d).reshape(nj * D * D, -1)
+        assert np.linalg.norm(vd @ (vd.T @ Mm) - Mm) > 1e-9 * nrm
+    # a whole solve with chi' = chi'' = chi is the default one
+    r0 = O.solve(A, B, 8, O.REDUCED, max_iters=3)
+    r1 = O.solve(A, B, 8, O.REDUCED, max_iters=3, chi_p=8, chi_pp=8)
+    assert r0["e_site"] == r1["e_site"]
