@@ -56,19 +56,13 @@ def f_move(d, D, chi):
     return 2.0 * ins
 
 
-def cpu_baseline(d, D, chi, seed=0):
-    """Time the FP64 oracle on a bounded sample of the same workload: one
-    reduced anchor, one edge absorption chain and two corner absorptions (a
-    quarter of a move) from a seeded random environment at full bond
-    dimension chi; the move time is four times the sample."""
+def _oracle_quarter_move(d, D, chi, seed):
+    """Seconds for one reduced anchor, one edge absorption chain and two
+    corner absorptions of the FP64 oracle (a quarter of a move) from a seeded
+    random environment at full bond dimension chi."""
     import numpy as np
     import oracle.ctm as OC
     from synth import site_tensors
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count() or 1
     A, B = site_tensors(d, D, seed)
     rng = np.random.default_rng(seed + 1000)
     env = {}
@@ -88,18 +82,94 @@ def cpu_baseline(d, D, chi, seed=0):
     np.einsum("mbp,mbn->pn", G4, v2, optimize=True)
     dt = time.perf_counter() - t0
     del T1n
+    return dt
+
+
+def cpu_baseline(d, D, chi, seed=0):
+    """The FP64 oracle timed on a bounded sample of the same workload (a
+    quarter of a move, see _oracle_quarter_move) with every host thread the
+    BLAS uses, and the same sample on one thread; moves/s = 1 / (4 t)."""
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threadpool_limits = None
+        cores = os.cpu_count() or 1
+    dt = _oracle_quarter_move(d, D, chi, seed)
+    dt1 = None
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            dt1 = _oracle_quarter_move(d, D, chi, seed)
     return {"value": 1.0 / (4.0 * dt), "unit": "moves/s", "cores": int(cores),
             "kind": "oracle",
+            "value_1_thread": (1.0 / (4.0 * dt1)) if dt1 else None,
             "sample": f"one reduced anchor + one edge chain + two corner absorptions "
                       f"(1/4 move) at d={d}, D={D}, chi={chi} from a seeded random "
-                      f"full-rank environment, FP64 NumPy, {dt:.1f} s; moves/s = 1/(4 t)"}
+                      f"full-rank environment, FP64 NumPy: {dt:.1f} s on {cores} threads, "
+                      f"{dt1:.1f} s on 1 thread; moves/s = 1/(4 t)" if dt1 else
+                      f"one reduced anchor + one edge chain + two corner absorptions "
+                      f"(1/4 move) at d={d}, D={D}, chi={chi}, FP64 NumPy, {dt:.1f} s"}
+
+
+def method_comparison(d=2, D=4, chi=64, moves=8, oracle_moves=1, seed=0):
+    """Time per move of the three isometry methods at one size, FP64 on the
+    GPU (graph replay, after the bootstrap iteration and a warm-up
+    iteration) and in the oracle (one move after the bootstrap, on the
+    host's BLAS threads): the analogue of the paper's timing comparison of
+    standard, reduced-env and sequential-order CTM (Sec. V, Fig. 7)."""
+    import numpy as np
+    import torch
+    import oracle as O
+    import paper_2306_08212_amd as P
+    from synth import site_tensors
+    A, B = site_tensors(d, D, seed)
+    out = {"workload": f"d={d}, D={D}, chi={chi}, FP64, one directional move", "gpu_ms": {},
+           "oracle_ms": {}}
+    for name, pm, om in (("standard", P.STANDARD, O.STANDARD), ("reduced_env", P.REDUCED_ENV,
+                          O.REDUCED_ENV), ("sequential", P.REDUCED, O.REDUCED)):
+        s = P.Solver(P.Config(d=d, D=D, chi=chi, method=pm, precision=P.FP64), A, B)
+        s.iterate(2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(moves):
+            s.move(MOVE_ORDER[s.moves_done % 4])
+        torch.cuda.synchronize()
+        out["gpu_ms"][name] = 1e3 * (time.perf_counter() - t0) / moves
+        s.close()
+        env = O.ctm_iteration(O.init_env(A, B), A, B, chi, om)
+        t0 = time.perf_counter()
+        for i in range(oracle_moves):
+            env = O.move(env, A, B, MOVE_ORDER[i % 4], chi, om)
+        out["oracle_ms"][name] = 1e3 * (time.perf_counter() - t0) / oracle_moves
+        log(f"bench: method {name}: gpu {out['gpu_ms'][name]:.2f} ms/move, "
+            f"oracle {out['oracle_ms'][name]:.0f} ms/move")
+    return out
+
+
+def _breakdown(results):
+    """Per-(D, chi band) solve count, p50 latency and mean iterations."""
+    import numpy as np
+    groups = {}
+    for r in results:
+        if r.status != "ok":
+            continue
+        band = "chi<=64" if r.chi <= 64 else ("chi<=144" if r.chi <= 144 else "chi<=256")
+        groups.setdefault(f"D={r.D},{band}", []).append(r)
+    out = {}
+    for k in sorted(groups):
+        lat = sorted(x.latency for x in groups[k])
+        out[k] = {"solves": len(lat), "p50_s": float(np.median(lat)),
+                  "mean_iters": float(np.mean([x.iters for x in groups[k]]))}
+    return out
 
 
 def serve_stream(args):
-    """Serving: independent solves with D uniform in {3..dmax}, chi uniform in
-    [D^2, min(4 D^2, 256)], FP32 chains, a fixed number of iterations each.
-    First all requests at once (closed loop) to find the saturated rate mu,
-    then a seeded Poisson stream at 0.8 mu for latency percentiles."""
+    """Serving: the stream of independent solves of the serving workload --
+    D uniform in {3..dmax}, chi uniform in [D^2, min(4 D^2, 256)], FP32
+    chains, each until delta < tol or max_iters iterations.  First all
+    requests at t = 0 (closed loop) for the saturated rate mu, then a seeded
+    Poisson stream at 0.8 mu for the latency percentiles; admission by the
+    HBM budget (0.8 of free memory) and up to 16 solves in flight."""
     from paper_2306_08212_amd.serve import GpuBackend, Request, Server, summarize
     from synth import serving_stream
     be = GpuBackend()
@@ -109,19 +179,28 @@ def serve_stream(args):
         for q in serving_stream(n, seed, rate, d=args.d, D_min=3, D_max=args.serve_dmax):
             out.append(Request(id=q["id"], d=q["d"], D=q["D"], chi=q["chi"], seed=q["seed"],
                                t_arrival=q["t_arrival"], max_iters=args.serve_iters,
-                               tol=0.0, precision=1))
+                               tol=args.serve_tol, precision=1))
         return out
 
-    n_closed = max(8, args.serve_requests // 2)
-    closed = summarize(Server(be, max_slots=16).run(reqs(n_closed, 7, 0.0)))
+    n = args.serve_requests
+
+    def progress(r):
+        log(f"bench: served request {r.id} (D={r.D}, chi={r.chi}, {r.iters} iterations, "
+            f"{r.latency:.2f} s)")
+
+    res_closed = Server(be, max_slots=16, on_result=progress).run(reqs(n, 7, 0.0))
+    closed = summarize(res_closed)
     mu = closed["solves_per_s"] or 1.0
     log(f"bench: serving closed loop {closed}")
     rate = 0.8 * mu
-    opened = summarize(Server(be, max_slots=16).run(reqs(args.serve_requests, 8, rate)))
+    res_open = Server(be, max_slots=16, on_result=progress).run(reqs(n, 8, rate))
+    opened = summarize(res_open)
     log(f"bench: serving open loop at {rate:.2f}/s {opened}")
-    return {"workload": f"D uniform in 3..{args.serve_dmax}, chi uniform in [D^2, 4 D^2], "
-                        f"d={args.d}, {args.serve_iters} iterations each, FP32 chains",
-            "closed_loop": closed, "open_loop_rate_per_s": rate, "open_loop": opened}
+    return {"workload": f"{n} solves, D uniform in 3..{args.serve_dmax}, chi uniform in "
+                        f"[D^2, min(4 D^2, 256)], d={args.d}, FP32 chains, until delta < "
+                        f"{args.serve_tol:g} or {args.serve_iters} iterations",
+            "closed_loop": closed, "open_loop_rate_per_s": rate, "open_loop": opened,
+            "open_loop_by_D_chi": _breakdown(res_open)}
 
 
 def main():
@@ -139,12 +218,23 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=4,
                     help="moves timed again with FP64 chains (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--serve-requests", type=int, default=24,
-                    help="requests in the open-loop serving stream (0 = skip serving)")
-    ap.add_argument("--serve-dmax", type=int, default=3,
+    ap.add_argument("--serve-requests", type=int, default=32,
+                    help="requests in each serving stream (the full serving workload is "
+                         "512; 0 = skip serving)")
+    ap.add_argument("--serve-dmax", type=int, default=8,
                     help="largest D in the serving stream (D uniform in 3..dmax)")
-    ap.add_argument("--serve-iters", type=int, default=8, help="iterations per served solve")
+    ap.add_argument("--serve-iters", type=int, default=30, help="iteration cap per solve")
+    ap.add_argument("--serve-tol", type=float, default=1e-6, help="delta that ends a solve")
+    ap.add_argument("--no-methods", action="store_true",
+                    help="skip the standard / reduced-env / sequential comparison")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--method-sweep", action="store_true",
+                    help="only time the three isometry methods (FP64, GPU) at D = 4..8 with the "
+                         "paper's chi = 10 (D + 1) and print one JSON line per D, then exit")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 20 plain device copies of MIB MiB through the library's "
+                         "permute kernel (identity permutation) and exit: the reference for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings to bytes")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -157,8 +247,63 @@ def main():
     import paper_2306_08212_amd as P
     from synth import site_tensors
 
-    P.load()   # fails loudly if libctm.so is missing
+    lib = P.load()   # fails loudly if libctm.so is missing
     torch.cuda.set_device(0)
+    if args.method_sweep:
+        for Dm in range(4, 9):
+            chim = 10 * (Dm + 1)
+            row = {"D": Dm, "chi": chim, "gpu_ms_per_move": {}}
+            Am, Bm = site_tensors(args.d, Dm, args.seed)
+            for name, pm in (("standard", P.STANDARD), ("reduced_env", P.REDUCED_ENV),
+                             ("sequential", P.REDUCED)):
+                sm = P.Solver(P.Config(d=args.d, D=Dm, chi=chim, method=pm, precision=P.FP64),
+                              Am, Bm)
+                sm.iterate(1)
+                for i in range(4):
+                    sm.move(MOVE_ORDER[sm.moves_done % 4])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for i in range(4):
+                    sm.move(MOVE_ORDER[sm.moves_done % 4])
+                torch.cuda.synchronize()
+                row["gpu_ms_per_move"][name] = 1e3 * (time.perf_counter() - t0) / 4
+                sm.close()
+                log(f"bench: D={Dm} chi={chim} {name}: {row['gpu_ms_per_move'][name]:.1f} ms/move")
+            print(json.dumps(row), flush=True)
+        # the headline size, mixed precision: the two reduced methods
+        row = {"D": 8, "chi": 256, "precision": "fp32", "gpu_ms_per_move": {}}
+        Am, Bm = site_tensors(args.d, 8, args.seed)
+        for name, pm in (("reduced_env", P.REDUCED_ENV), ("sequential", P.REDUCED)):
+            sm = P.Solver(P.Config(d=args.d, D=8, chi=256, method=pm, precision=P.FP32), Am, Bm)
+            sm.iterate(1)
+            for i in range(4):
+                sm.move(MOVE_ORDER[sm.moves_done % 4])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(4):
+                sm.move(MOVE_ORDER[sm.moves_done % 4])
+            torch.cuda.synchronize()
+            row["gpu_ms_per_move"][name] = 1e3 * (time.perf_counter() - t0) / 4
+            sm.close()
+            log(f"bench: D=8 chi=256 fp32 {name}: {row['gpu_ms_per_move'][name]:.1f} ms/move")
+        print(json.dumps(row), flush=True)
+        return
+    if args.copy_probe > 0:
+        import ctypes
+        n = args.copy_probe * (1 << 20) // 8
+        x = torch.ones(n, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        dims = (ctypes.c_int64 * 1)(n)
+        perm = (ctypes.c_int * 1)(0)
+        st = torch.cuda.current_stream().cuda_stream
+        for _ in range(20):
+            rc = lib.ctm_kernel_permute(0, x.data_ptr(), 1, dims, perm, 0, y.data_ptr(), 1.0, st)
+            if rc != 0:
+                raise RuntimeError(f"copy probe: status {rc}")
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 8, "copy_probe_bytes_written": n * 8,
+                          "launches": 20}), flush=True)
+        return
     d, D, chi = args.d, args.D, args.chi
     A, B = site_tensors(d, D, args.seed)
     cfg = P.Config(d=d, D=D, chi=chi, method=P.REDUCED, precision=P.PRECISIONS[args.precision])
@@ -235,6 +380,12 @@ def main():
             rec["gb_per_s"] = gbs
             rec["frac_of_peak"] = gbs / 8000.0
     gemm_flops = sum(prof[k][2] for k in ("gemm_f64", "gemm_f32", "gemm_bf16")) / nprof
+    # the truncation (FP64 SVDs, their QR steps and GEMMs, norms) against
+    # the absorption chains (FP32 / BF16 GEMMs and permutes), as shares of
+    # the summed kernel time of a move
+    trunc_cls = ("gemm_f64", "svd_round", "svd_other", "chol", "reduce")
+    total_k = sum(v[1] for v in prof.values())
+    trunc_share = sum(prof[k][1] for k in trunc_cls if k in prof) / total_k if total_k else None
 
     fp64_mps = None
     if args.fp64_steps > 0 and args.precision != "fp64":
@@ -244,6 +395,10 @@ def main():
         ms64, _ = timed(args.fp64_steps, "fp64")
         fp64_mps = args.fp64_steps / (ms64 / 1e3)
     s.close()
+
+    methods = None
+    if not args.no_methods:
+        methods = method_comparison(d=d)
 
     serving = None
     if args.serve_requests > 0:
@@ -279,6 +434,8 @@ def main():
                        "frac_of_fp32_mfma_peak": fm * moves_per_s / 157.3e12,
                        "gemm_flop_per_move_measured": gemm_flops},
         "fp64_moves_per_s": fp64_mps,
+        "truncation_share": trunc_share,
+        "method_comparison": methods,
         "serving": serving,
         "kernel_breakdown": breakdown,
         "cpu_baseline": cpu,

@@ -62,8 +62,11 @@ enum ctm_status {
 };
 
 enum ctm_method {
-  CTM_STANDARD = 0,  /* standard isometries every move (Sec. II)             */
-  CTM_REDUCED = 1    /* sequential-order isometries (Secs. III-IV, App.)     */
+  CTM_STANDARD = 0,   /* standard isometries every move (Sec. II)            */
+  CTM_REDUCED = 1,    /* sequential-order isometries (Secs. III-IV, App.)    */
+  CTM_REDUCED_ENV = 2 /* reduced-env: one 4-index isometry from the reduced
+                         half-network [C1 T2 C2; T1 z T3] (Sec. III,
+                         Fig. 3(a,b)), cost chi^3 D^4                        */
 };
 
 enum ctm_precision {
@@ -88,6 +91,13 @@ typedef struct {
   void *stream;          /* hipStream_t the solver is bound to; NULL = null stream */
   void *workspace;       /* caller-owned device memory, >= ctm_workspace_size */
   size_t workspace_bytes;
+  int chi_p;             /* chi': bond of the first-stage isometry v^1 of the
+                            sequential-order split (Sec. IV: "slightly larger
+                            chi'" for strongly correlated states); 0 = chi,
+                            else >= chi                                      */
+  int chi_pp;            /* chi'': bond of the first stage of the helper
+                            isometries v_l^1, v_r^1 (App.); 0 = chi, else
+                            >= chi.  Sec. V sets both to chi.                */
 } ctm_config;
 
 /* Exact peak device bytes one solver uses for cfg (all of it inside the
@@ -151,6 +161,24 @@ int ctm_read_delta(ctm_solver *s, double *delta);
  * (a above b), vertical (b above a).  Synchronises the stream.  CTM_ENUMERIC
  * for a non-finite or zero-trace result or a pending numeric error. */
 int ctm_energy(ctm_solver *s, const double *h2, double *e_site, double e_bond[4]);
+
+/* One-site expectation values out[0] = <op>_a, out[1] = <op>_b of a d x d
+ * host operator op[s'][s] (row-major, acting on the ket index s), each from
+ * the site between its four corners and four edges: <op> = tr(rho op) /
+ * tr(rho).  Sec. V: the staggered magnetisation of the Heisenberg model
+ * (|<S>_a - <S>_b| / 2), the order parameter m_z = <S^z> and the
+ * transverse-field term <S^x> of the Ising model.  Synchronises the stream;
+ * CTM_EINVAL for NULL pointers, CTM_ENUMERIC for a non-finite result. */
+int ctm_expect1(ctm_solver *s, const double *op, double out[2]);
+
+/* Connected correlation along a row, out[x-1] = <op_0 op_x> - <op_0><op_x>
+ * for x = 1..L (1 <= L <= 4096), with site 0 on sublattice a and the row
+ * horizontal (Sec. V, Fig. 8(b): S_zz(x) at the Ising critical point).  The
+ * row between the edges above and below it is contracted column by column
+ * from the left boundary of site 0 to the right boundary of site x (ket
+ * layer before bra layer, chi^3 D^4 + chi^2 D^6 d per column).  op as for
+ * ctm_expect1.  Synchronises the stream. */
+int ctm_row_correlation(ctm_solver *s, const double *op, int L, double *out);
 
 /* Copy environment tensor e (0..15, see above) to host memory: writes its two
  * boundary dimensions to *p, *q and, if host_out is not NULL and n is large

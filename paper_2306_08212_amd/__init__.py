@@ -20,14 +20,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libctm.so")
 
 CTM_OK, CTM_EINVAL, CTM_ENOMEM, CTM_EHIP, CTM_ENUMERIC, CTM_ENOTCONV = range(6)
-STANDARD, REDUCED = 0, 1
+STANDARD, REDUCED, REDUCED_ENV = 0, 1, 2
 FP64, FP32, BF16 = 0, 1, 2
 LEFT, UP, RIGHT, DOWN = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16": BF16}
-METHODS = {"standard": STANDARD, "reduced": REDUCED}
+METHODS = {"standard": STANDARD, "reduced": REDUCED, "reduced_env": REDUCED_ENV}
 
 EXPORTS = ["ctm_workspace_size", "ctm_init", "ctm_move", "ctm_iterate", "ctm_converge",
-           "ctm_iterate_delta", "ctm_read_delta", "ctm_energy", "ctm_get_env", "ctm_set_env", "ctm_moves_done", "ctm_set_precision", "ctm_set_graphs",
+           "ctm_iterate_delta", "ctm_read_delta", "ctm_energy", "ctm_expect1", "ctm_row_correlation", "ctm_get_env", "ctm_set_env", "ctm_moves_done", "ctm_set_precision", "ctm_set_graphs",
            "ctm_profile", "ctm_profile_read", "ctm_destroy",
            "ctm_status_string", "ctm_kernel_gemm", "ctm_kernel_tsvd", "ctm_kernel_tsvd_workspace",
            "ctm_kernel_permute", "ctm_kernel_tsvd_static", "ctm_kernel_tsvd_static_max"]
@@ -38,7 +38,8 @@ class CtmConfig(ctypes.Structure):
                 ("method", ctypes.c_int), ("precision", ctypes.c_int),
                 ("boot_iters", ctypes.c_int), ("svd_cutoff", ctypes.c_double),
                 ("stream", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
-                ("workspace_bytes", ctypes.c_size_t)]
+                ("workspace_bytes", ctypes.c_size_t), ("chi_p", ctypes.c_int),
+                ("chi_pp", ctypes.c_int)]
 
 
 class CtmError(RuntimeError):
@@ -107,6 +108,10 @@ def load(path: str = LIB_PATH):
     lib.ctm_kernel_tsvd.restype = I
     lib.ctm_kernel_tsvd_workspace.argtypes = [I, I, I]
     lib.ctm_kernel_tsvd_workspace.restype = ctypes.c_size_t
+    lib.ctm_expect1.argtypes = [P, P, ctypes.POINTER(D)]
+    lib.ctm_expect1.restype = I
+    lib.ctm_row_correlation.argtypes = [P, P, I, ctypes.POINTER(D)]
+    lib.ctm_row_correlation.restype = I
     lib.ctm_kernel_tsvd_static.argtypes = [P, I, I, I, D, P, P, P]
     lib.ctm_kernel_tsvd_static.restype = I
     lib.ctm_kernel_tsvd_static_max.argtypes = []
@@ -140,11 +145,13 @@ class Config:
     precision: int = FP64
     boot_iters: int = 0
     svd_cutoff: float = 1e-14
+    chi_p: int = 0          # chi' of the sequential-order split (0 = chi)
+    chi_pp: int = 0         # chi'' of the helper isometries (0 = chi)
 
     def to_c(self, stream=0, workspace=0, nbytes=0) -> CtmConfig:
         return CtmConfig(self.d, self.D, self.chi, self.method, self.precision,
                          self.boot_iters, self.svd_cutoff, stream or None,
-                         workspace or None, nbytes)
+                         workspace or None, nbytes, self.chi_p, self.chi_pp)
 
 
 def workspace_size(cfg: Config) -> int:
@@ -227,6 +234,30 @@ class Solver:
             hp = h2.ctypes.data
         _check(load().ctm_energy(self.handle, hp, ctypes.byref(e), eb), "ctm_energy")
         return e.value, list(eb)
+
+    def expect1(self, op: np.ndarray):
+        """(<op>_a, <op>_b) of a d x d one-site operator (ctm_expect1)."""
+        op = np.ascontiguousarray(op, dtype=np.float64)
+        out = (ctypes.c_double * 2)()
+        _check(load().ctm_expect1(self.handle, op.ctypes.data, out), "ctm_expect1")
+        return list(out)
+
+    def staggered_magnetisation(self) -> float:
+        """|<S>_a - <S>_b| / 2 with S = sigma / 2; <S^y> = 0 for real tensors."""
+        sx = np.array([[0.0, 0.5], [0.5, 0.0]])
+        sz = np.array([[0.5, 0.0], [0.0, -0.5]])
+        xa, xb = self.expect1(sx)
+        za, zb = self.expect1(sz)
+        return 0.5 * float(np.hypot(xa - xb, za - zb))
+
+    def row_correlation(self, op: np.ndarray, L: int):
+        """[C(1), ..., C(L)], C(x) = <op_0 op_x> - <op_0><op_x> along a row
+        from an a-site (ctm_row_correlation)."""
+        op = np.ascontiguousarray(op, dtype=np.float64)
+        out = (ctypes.c_double * L)()
+        _check(load().ctm_row_correlation(self.handle, op.ctypes.data, L, out),
+               "ctm_row_correlation")
+        return list(out)
 
     def get_env(self, e: int) -> np.ndarray:
         lib = load()

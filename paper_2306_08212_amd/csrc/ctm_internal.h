@@ -90,7 +90,7 @@ struct Ctx {
   Arena arena;
   bool dry = false;
   hipError_t hip_err = hipSuccess;
-  int* dev_flags = nullptr;   // [0] numeric error bits (1 bad norm, 2 SVD not converged)
+  int* dev_flags = nullptr;   // [0] error bits (1 bad norm, 2 SVD not converged, 4 guard hit)
   double* work = nullptr;     // device tallies of data-dependent work (profiling)
   uint64_t rng_calls = 0;     // counter of randomised truncations (seeds)
   void check(hipError_t e) {
@@ -172,6 +172,20 @@ void max_abs_diff(Ctx& c, const double* a, const double* b, int n, double* out);
 
 // Contract the reduced density matrix with h: out[0] = sum rho*h, out[1] = tr rho.
 void rho_energy(Ctx& c, const double* rho, const double* h4, int d, double* out);
+
+// One-site density matrix rho[s, S] with op[S, s] (d x d): out[0] = sum
+// rho op, out[1] = tr rho.
+void rho1_expect(Ctx& c, const double* rho, const double* op, int d, double* out);
+
+// Connected correlation <op op> - <op><op> from the d x d right-end
+// matrices with op (RO) and with the identity (RI) on the left site.
+void corr_finish(Ctx& c, const double* RO, const double* RI, const double* op, int d,
+                 double* out);
+
+// Debug guard regions: fill with a sentinel; check sets bit 4 of the error
+// word if any byte changed.
+void guard_fill(Ctx& c, void* p, size_t bytes);
+void guard_check(Ctx& c, const void* p, size_t bytes);
 
 // General contraction helper: out(lo) = A(la) * B(lb), labels are single
 // characters; no label may appear in all three.  compute: F64/F32/BF16;

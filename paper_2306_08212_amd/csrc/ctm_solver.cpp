@@ -26,6 +26,9 @@ using namespace ctm;
 struct ctm_solver {
   Ctx ctx;
   int d = 2, D = 1, chi = 1, method = CTM_REDUCED, precision = CTM_FP64, boot_iters = 1;
+  // first-stage bonds of the sequential-order split: chi_p of the anchors'
+  // v^1 (Sec. IV), chi_pp of the helper isometries v_l^1, v_r^1 (App.)
+  int chi_p = 1, chi_pp = 1;
   double tau = 1e-14;
   int cap = 1;        // largest bond dimension any tensor can take
   int moves = 0;
@@ -73,6 +76,7 @@ struct ctm_solver {
 namespace {
 
 constexpr int kC = 0, kT = 1;
+constexpr int kMaxCorrLength = 4096;   // longest row of ctm_row_correlation
 
 inline int env_index(int kind, int i, int z) { return 8 * kind + 2 * (i - 1) + z; }
 inline int stored_i(int i, int r) { return (i - 1 + r) % 4 + 1; }
@@ -127,10 +131,20 @@ void run_branches(ctm_solver* s, const std::vector<std::function<void(Ctx&)>>& f
     need[b] = d.arena.peak + 256;
   }
   // the slices are released on return: every later use of that memory is
-  // ordered after the join on ctx.stream
+  // ordered after the join on ctx.stream.  With CTM_DEBUG_GUARD set, each
+  // slice is followed by a guard region checked after the join (a write
+  // past a slice would land in the next branch's memory and make results
+  // depend on timing); a hit sets bit 4 of the error word.
+  const bool guard = std::getenv("CTM_DEBUG_GUARD") != nullptr;
+  const size_t gbytes = guard ? ((size_t)1 << 16) : 0;
   const size_t mk = c.arena.mark();
-  std::vector<char*> base(n);
-  for (int b = 0; b < n; ++b) base[b] = (char*)c.arena.alloc(need[b]);
+  std::vector<char*> base(n), gbase(n);
+  for (int b = 0; b < n; ++b) {
+    base[b] = (char*)c.arena.alloc(need[b]);
+    gbase[b] = gbytes ? (char*)c.arena.alloc(gbytes) : nullptr;
+  }
+  if (gbytes && !c.dry)
+    for (int b = 0; b < n; ++b) guard_fill(c, gbase[b], gbytes);
   if (c.dry && std::getenv("CTM_DEBUG_MEM"))
     for (int b = 0; b < n; ++b)
       std::fprintf(stderr, "  branch %d/%d needs %.1f MB (top %.1f MB)\n", b, n, need[b] / 1e6,
@@ -234,17 +248,22 @@ void run_branches(ctm_solver* s, const std::vector<std::function<void(Ctx&)>>& f
   }
   if (par)
     for (int b = 0; b < n; ++b) c.check(hipStreamWaitEvent(c.stream, s->ev_join[b], 0));
+  if (gbytes)
+    for (int b = 0; b < n; ++b) guard_check(c, gbase[b], gbytes);
   c.arena.release(mk);
   for (int b = 0; b < n; ++b)
     if (errs[b]) std::rethrow_exception(errs[b]);
 }
 
-// Truncated isometry of a row-major m x n F64 matrix: U (m x kk) at dst.
-Tensor isometry(ctm_solver* s, Ctx& c, const Tensor& M, int64_t m, int64_t n, void* dst) {
-  const int kk = (int)std::min<int64_t>(s->chi, std::min(m, n));
+// Truncated isometry of a row-major m x n F64 matrix: U (m x kk) at dst,
+// kk = min(k, m, n) (k = chi unless given).
+Tensor isometry(ctm_solver* s, Ctx& c, const Tensor& M, int64_t m, int64_t n, void* dst,
+                int k = 0) {
+  if (k <= 0) k = s->chi;
+  const int kk = (int)std::min<int64_t>(k, std::min(m, n));
   const size_t mk = c.arena.mark();
   double* S = (double*)c.arena.alloc(sizeof(double) * std::max(kk, 1));
-  tsvd(c, M.d(), (int)m, (int)n, s->chi, s->tau, (double*)dst, S);
+  tsvd(c, M.d(), (int)m, (int)n, k, s->tau, (double*)dst, S);
   c.arena.release(mk);
   return make_view(dst, F64, {m, kk});
 }
@@ -279,6 +298,46 @@ Tensor anchor_standard(ctm_solver* s, Ctx& c, int r, int z, void* dst) {
   return make_view(dst, F64, {nj, D, D, U.dims[1]});
 }
 
+// Reduced-env 4-index isometry v_z[j, kd, bd, nu] (Sec. III, Fig. 3(a,b)):
+// in a converged environment the right half of the half-plaquette,
+// {w, T2_w, C2_w, T3_w}, is stood in for by the anchor's own {C2_z, T3_z}
+// (the right move's isometry that would follow is dropped: multiplying by a
+// co-isometry from the right leaves the left singular vectors unchanged).
+// The reduced half-network [C1 T2 C2; T1 z T3] is contracted with the ket
+// layer of z before the bra layer, so it costs chi^3 D^4 + chi^2 D^6 d,
+// reshaped (chi D^2) x chi and truncated to its top chi left singular
+// vectors.
+Tensor anchor_reduced_env(ctm_solver* s, Ctx& c, int r, int z, void* dst) {
+  const int64_t D = s->D;
+  Tensor C1 = env_view(s, kC, 1, z, r), T1 = env_view(s, kT, 1, z, r), T2 = env_view(s, kT, 2, z, r);
+  Tensor C2 = env_view(s, kC, 2, z, r), T3 = env_view(s, kT, 3, z, r);
+  const int64_t nj = T1.dims[0], nj2 = T3.dims[3];
+  const size_t mk = c.arena.mark();
+  Tensor Az = site_view(s, r, z);
+  Tensor L = contract(c, C1, "mi", T1, "jklm", "iklj", F64, F64);
+  Tensor R = contract(c, C2, "im", T3, "mklj", "iklj", F64, F64);
+  Tensor X = contract(c, L, "iklj", T2, "iuvn", "kljuvn", F64, F64);
+  X = contract(c, X, "kljuvn", Az, "skurd", "ljvnsrd", F64, F64);     // ket layer
+  X = contract(c, X, "ljvnsrd", Az, "slvRD", "jnrdRD", F64, F64);     // bra layer
+  Tensor M = contract(c, X, "jnrdRD", R, "nrRk", "jdDk", F64, F64);
+  Tensor U = isometry(s, c, M, nj * D * D, nj2, dst);
+  c.arena.release(mk);
+  return make_view(dst, F64, {nj, D, D, U.dims[1]});
+}
+
+// Absorption of one site into an edge with 4-index isometries on both bonds
+// (Sec. II, Fig. 2(b)), ket layer then bra layer: T[p,k,b,q] with the
+// q-side bond (q, ku, bu) truncated by vq[q,u,v,n] and the p-side bond
+// (p, kd, bd) by vp[p,d,D,m]; site A[s,l,u,r,d] of the frame, its l leg on
+// T's (k, b).  Returns out[m, kr, br, n] in F64; the contractions run in
+// the compute type cp (chi^3 D^4 + chi^2 D^6 d, no double-layer tensor).
+Tensor absorb4(Ctx& c, const Tensor& T, const Tensor& A, const Tensor& vp, const Tensor& vq, int cp) {
+  Tensor Z = contract(c, T, "pklq", vq, "quvn", "pkluvn", cp, cp);
+  Z = contract(c, Z, "pkluvn", A, "skurd", "plvnsrd", cp, cp);         // ket layer
+  Z = contract(c, Z, "plvnsrd", A, "slvRD", "pnrdRD", cp, cp);         // bra layer
+  return contract(c, Z, "pnrdRD", vp, "pdDm", "mrRn", cp, F64);
+}
+
 // Two-stage isometry of X[i,k,b,j] (bonded on (i,k,b)): v1 [i,k,mu], v2
 // [mu,b,nu], X''[nu,j] (Appendix, Fig. A(c)).  Outputs at the given buffers.
 //
@@ -293,7 +352,7 @@ void split_iso(ctm_solver* s, Ctx& c, const Tensor& X, void* d1, void* d2, void*
                Tensor* v1o, Tensor* v2o, Tensor* xxo) {
   const int64_t ni = X.dims[0], D = X.dims[1], nj = X.dims[3];
   const size_t mk = c.arena.mark();
-  Tensor v1 = isometry(s, c, X, ni * D, D * nj, d1);
+  Tensor v1 = isometry(s, c, X, ni * D, D * nj, d1, s->chi_pp);
   const int64_t c1 = v1.dims[1];
   v1 = reshape(v1, {ni, D, c1});
   Tensor Xp = contract(c, v1, "ikm", X, "iklj", "mlj", F64, F64);
@@ -371,7 +430,7 @@ SplitV anchor_reduced(ctm_solver* s, Ctx& c, int r, int z, const SideIso& L, con
   Tensor Tp2 = chain(s, c, T2, S, L.v1, L.v2, R.v1, R.v2);
   Tensor Mp = contract(c, L.cc, "nj", Tp2, "ndDo", "jdDo", F64, F64);
   Mp = contract(c, Mp, "jdDo", R.cc, "ok", "jdDk", F64, F64);
-  Tensor v1 = isometry(s, c, Mp, nj * D, D * nj2, d1);
+  Tensor v1 = isometry(s, c, Mp, nj * D, D * nj2, d1, s->chi_p);
   const int64_t c1 = v1.dims[1];
   v1 = reshape(v1, {nj, D, c1});
   Tensor N = contract(c, v1, "jdm", Mp, "jdDk", "mDk", F64, F64);
@@ -382,6 +441,11 @@ SplitV anchor_reduced(ctm_solver* s, Ctx& c, int r, int z, const SideIso& L, con
   return SplitV{v1, v2};
 }
 
+// Whether an insertion in frame r uses the standard isometries: always for
+// the standard method and during the first boot_iters iterations, and
+// otherwise whenever the reduced rule would leave a new bond smaller, by
+// shape, than the standard one (the reduced sub-networks have rank at most
+// the far-side bond T3.q, so they cannot grow a bond).
 bool insertion_standard(const ctm_solver* s, int r) {
   if (s->method == CTM_STANDARD) return true;
   if (s->moves / 4 < s->boot_iters) return true;
@@ -390,8 +454,13 @@ bool insertion_standard(const ctm_solver* s, int r) {
     const int64_t nj = s->pd[env_index(kT, stored_i(1, r), z)];
     const int64_t nj2 = s->qd[env_index(kT, stored_i(3, r), z)];
     const int64_t sd = std::min({chi, nj * D * D, D * D * nj2});
-    const int64_t c1 = std::min({chi, nj * D, D * nj2});
-    const int64_t rd = std::min({chi, c1 * D, nj2});
+    int64_t rd;
+    if (s->method == CTM_REDUCED_ENV) {
+      rd = std::min({chi, nj * D * D, nj2});
+    } else {
+      const int64_t c1 = std::min({(int64_t)s->chi_p, nj * D, D * nj2});
+      rd = std::min({chi, c1 * D, nj2});
+    }
     if (rd < sd) return true;
   }
   return false;
@@ -418,18 +487,24 @@ void insert_column(ctm_solver* s, int r, SideIso* rside, bool have_r) {
   Ctx& c = s->ctx;
   const int64_t D = s->D, cap = s->cap, chi = s->chi;
   const bool stdm = insertion_standard(s, r);
+  // 4-index isometries: standard (Sec. II) or reduced-env (Sec. III)
+  const bool four = stdm || s->method == CTM_REDUCED_ENV;
   // the standard move's (chi D^2) x (D^2 chi) objects dominate the
   // workspace; when they are large its branches run one after the other
-  const bool big_standard = (double)cap * D * D * cap * D * D * 8.0 > 1e9;
+  const bool big_standard = stdm && (double)cap * D * D * cap * D * D * 8.0 > 1e9;
   const size_t mk = c.arena.mark();
   // anchors
   Tensor V4[2];
   SplitV VS[2];
-  if (stdm) {
+  if (four) {
     void* dv[2];
     for (int z = 0; z < 2; ++z) dv[z] = c.arena.alloc(sizeof(double) * cap * D * D * chi);
-    auto a0 = [&](Ctx& k) { V4[0] = anchor_standard(s, k, r, 0, dv[0]); };
-    auto a1 = [&](Ctx& k) { V4[1] = anchor_standard(s, k, r, 1, dv[1]); };
+    auto a0 = [&](Ctx& k) {
+      V4[0] = stdm ? anchor_standard(s, k, r, 0, dv[0]) : anchor_reduced_env(s, k, r, 0, dv[0]);
+    };
+    auto a1 = [&](Ctx& k) {
+      V4[1] = stdm ? anchor_standard(s, k, r, 1, dv[1]) : anchor_reduced_env(s, k, r, 1, dv[1]);
+    };
     if (big_standard) {
       run_branches(s, {a0});
       run_branches(s, {a1});
@@ -439,8 +514,8 @@ void insert_column(ctm_solver* s, int r, SideIso* rside, bool have_r) {
   } else {
     SideIso side[2][2];   // [z][side]
     for (int z = 0; z < 2; ++z) {
-      side[z][0].b1 = c.arena.alloc(sizeof(double) * cap * D * chi);
-      side[z][0].b2 = c.arena.alloc(sizeof(double) * chi * D * chi);
+      side[z][0].b1 = c.arena.alloc(sizeof(double) * cap * D * s->chi_pp);
+      side[z][0].b2 = c.arena.alloc(sizeof(double) * s->chi_pp * D * chi);
       side[z][0].bc = c.arena.alloc(sizeof(double) * chi * cap);
       side[z][1] = rside[z];
     }
@@ -454,8 +529,8 @@ void insert_column(ctm_solver* s, int r, SideIso* rside, bool have_r) {
     void* d1[2];
     void* d2[2];
     for (int z = 0; z < 2; ++z) {
-      d1[z] = c.arena.alloc(sizeof(double) * cap * D * chi);
-      d2[z] = c.arena.alloc(sizeof(double) * chi * D * chi);
+      d1[z] = c.arena.alloc(sizeof(double) * cap * D * s->chi_p);
+      d2[z] = c.arena.alloc(sizeof(double) * s->chi_p * D * chi);
     }
     run_branches(s, {[&](Ctx& k) { VS[0] = anchor_reduced(s, k, r, 0, side[0][0], side[0][1], d1[0], d2[0]); },
                      [&](Ctx& k) { VS[1] = anchor_reduced(s, k, r, 1, side[1][0], side[1][1], d1[1], d2[1]); }});
@@ -478,7 +553,7 @@ void insert_column(ctm_solver* s, int r, SideIso* rside, bool have_r) {
       const size_t m2 = k.arena.mark();
       Tensor G = contract(k, C1x, "jm", T2x, "mubq", "jubq", F64, F64);
       Tensor t;
-      if (stdm) {
+      if (four) {
         t = contract(k, G, "jubq", V4[y], "jubn", "nq", F64, F64);
       } else {
         Tensor G1 = contract(k, G, "jubq", VS[y].v1, "jum", "mbq", F64, F64);
@@ -490,11 +565,10 @@ void insert_column(ctm_solver* s, int r, SideIso* rside, bool have_r) {
     {
       const size_t m2 = k.arena.mark();
       Tensor t;
-      if (stdm) {
-        Tensor a = double_layer(k, site_view(s, r, x));
-        Tensor Z = contract(k, T1x, "pklq", V4[y], "quvn", "pkluvn", F64, F64);
-        Z = contract(k, Z, "pkluvn", a, "kluvrRdD", "pnrRdD", F64, F64);
-        t = contract(k, Z, "pnrRdD", V4[x], "pdDm", "mrRn", F64, F64);
+      if (four) {
+        // the standard bootstrap stays FP64; the reduced-env method absorbs
+        // in the compute type, like the sequential chains
+        t = absorb4(k, T1x, site_view(s, r, x), V4[x], V4[y], stdm ? F64 : cp);
       } else {
         Tensor S = make_view(s->sT1[r][x], cp, {s->d, D, D, D, D});
         t = chain(s, k, T1x, S, VS[x].v1, VS[x].v2, VS[y].v1, VS[y].v2);
@@ -506,7 +580,7 @@ void insert_column(ctm_solver* s, int r, SideIso* rside, bool have_r) {
       const size_t m2 = k.arena.mark();
       Tensor G4 = contract(k, C4x, "mj", T4x, "pkbm", "jkbp", F64, F64);
       Tensor t;
-      if (stdm) {
+      if (four) {
         t = contract(k, G4, "jkbp", V4[x], "jkbn", "pn", F64, F64);
       } else {
         Tensor G5 = contract(k, G4, "jkbp", VS[x].v1, "jkm", "mbp", F64, F64);
@@ -518,7 +592,7 @@ void insert_column(ctm_solver* s, int r, SideIso* rside, bool have_r) {
   };
   auto u0 = [&](Ctx& k) { update_row(k, 0); };
   auto u1 = [&](Ctx& k) { update_row(k, 1); };
-  if (stdm && big_standard) {
+  if (big_standard) {
     run_branches(s, {u0});
     run_branches(s, {u1});
   } else {
@@ -541,8 +615,8 @@ void do_move(ctm_solver* s, int r) {
   const size_t mk = c.arena.mark();
   SideIso rside[2];
   for (int z = 0; z < 2; ++z) {
-    rside[z].b1 = c.arena.alloc(sizeof(double) * cap * D * chi);
-    rside[z].b2 = c.arena.alloc(sizeof(double) * chi * D * chi);
+    rside[z].b1 = c.arena.alloc(sizeof(double) * cap * D * s->chi_pp);
+    rside[z].b2 = c.arena.alloc(sizeof(double) * s->chi_pp * D * chi);
     rside[z].bc = c.arena.alloc(sizeof(double) * chi * cap);
   }
   bool have_r = false;
@@ -649,6 +723,113 @@ void bond_energy(ctm_solver* s, int x, int r, double* out) {
   // its T4-bond index the T2_y.p bond: HR[t, i, r1, c, T, R1]
   Tensor rho = contract(c, HL, "scriSR", HR, "tircTR", "stST", F64, F64);
   rho_energy(c, rho.d(), s->h4, s->d, out);
+  c.arena.release(mk);
+}
+
+// Right boundary column {C2, T3, C3} of site x in frame r:
+// Rb[c, r1, R1, i] with c the bond to T2_x.q, (r1, R1) the legs into the
+// site's right leg and i the bond to T4_x.p.
+Tensor right_boundary(ctm_solver* s, Ctx& c, int x, int r) {
+  Tensor C2 = env_view(s, kC, 2, x, r), T3 = env_view(s, kT, 3, x, r), C3 = env_view(s, kC, 3, x, r);
+  Tensor X = contract(c, C2, "bn", T3, "ntTe", "btTe", F64, F64);
+  return contract(c, X, "btTe", C3, "eg", "btTg", F64, F64);
+}
+
+// Unnormalised one-site reduced density matrix rho[s, S] of an x-site (the
+// site between its four corners and four edges, Sec. II, Fig. 1(c)) into
+// out (d x d, device): the left half of the bond network closed by the
+// site's own right boundary.
+void site_rdm(ctm_solver* s, int x, double* out) {
+  Ctx& c = s->ctx;
+  const int64_t d = s->d, D = s->D;
+  const size_t mk = c.arena.mark();
+  const int64_t nc = env_view(s, kT, 2, x, 0).dims[3], ni = env_view(s, kT, 4, x, 0).dims[0];
+  void* bl = c.arena.alloc(sizeof(double) * d * nc * D * ni * d * D);
+  Tensor HL = half_network(s, x, 0, bl);
+  Tensor Rb = right_boundary(s, c, x, 0);
+  Tensor rho = contract(c, HL, "scriSR", Rb, "crRi", "sS", F64, F64);
+  keep(c, rho, out);
+  c.arena.release(mk);
+}
+
+// Absorb the column {T2_z, z, T4_z} (frame 0, identity on the site's
+// physical legs) into a left vector V[c, r, R, f]: c / f the bonds to the
+// next T2 / T4, (r, R) the ket / bra legs toward the next site.  Ket layer
+// before bra layer (chi^3 D^4 + chi^2 D^6 d).
+Tensor absorb_column(ctm_solver* s, Ctx& c, const Tensor& V, int z) {
+  Tensor T2 = env_view(s, kT, 2, z, 0), T4 = env_view(s, kT, 4, z, 0);
+  Tensor A = site_view(s, 0, z);
+  Tensor X = contract(c, V, "crRf", T2, "cuUb", "rRfuUb", F64, F64);
+  X = contract(c, X, "rRfuUb", A, "srutd", "RfUbstd", F64, F64);
+  X = contract(c, X, "RfUbstd", A, "sRUTD", "fbtdTD", F64, F64);
+  return contract(c, X, "fbtdTD", T4, "gdDf", "btTg", F64, F64);
+}
+
+// <op> numerators and traces of the a- and b-site into out[0..3]
+// (numerator a, trace a, numerator b, trace b); op is d x d on the device.
+void expect1_impl(ctm_solver* s, const double* op, double* out) {
+  Ctx& c = s->ctx;
+  const int d = s->d;
+  const size_t mk = c.arena.mark();
+  double* rho = (double*)c.arena.alloc(sizeof(double) * d * d);
+  for (int z = 0; z < 2; ++z) {
+    site_rdm(s, z, rho);
+    rho1_expect(c, rho, op, d, out + 2 * z);
+  }
+  c.arena.release(mk);
+}
+
+// Connected correlation C(x) = <op_0 op_x> - <op_0><op_x> along a row of
+// frame 0 for x = 1..L into out (device), site 0 on sublattice a (Sec. V,
+// Fig. 8(b)).  Two left vectors, with op and with the identity on site 0,
+// are carried along the row column by column (both divided by the norm of
+// the identity one after each column, so their ratios are unchanged); at
+// each x they are closed with the right half of the site at x.
+void row_corr_impl(ctm_solver* s, const double* op, int L, double* out) {
+  Ctx& c = s->ctx;
+  const int64_t d = s->d, D = s->D, cap = s->cap;
+  const size_t mk = c.arena.mark();
+  double* nrm = (double*)c.arena.alloc(sizeof(double));
+  Tensor opT = make_view((void*)op, F64, {d, d});
+  Tensor I = c.alloc(F64, {d, d});
+  fill(c, I.p, F64, d * d, 0.0);
+  for (int64_t k = 0; k < d; ++k) fill(c, I.d() + k * (d + 1), F64, 1, 1.0);
+  Tensor HR[2];
+  for (int z = 0; z < 2; ++z) {
+    const int64_t nc = env_view(s, kT, 2, z, 2).dims[3], ni = env_view(s, kT, 4, z, 2).dims[0];
+    void* b = c.arena.alloc(sizeof(double) * d * nc * D * ni * d * D);
+    HR[z] = half_network(s, z, 2, b);
+  }
+  const size_t vbytes = sizeof(double) * cap * D * D * cap;
+  void* vo_buf = c.arena.alloc(vbytes);
+  void* vi_buf = c.arena.alloc(vbytes);
+  Tensor VO, VI;
+  {
+    const size_t m2 = c.arena.mark();
+    const int64_t nc = env_view(s, kT, 2, 0, 0).dims[3], ni = env_view(s, kT, 4, 0, 0).dims[0];
+    void* bl = c.arena.alloc(sizeof(double) * d * nc * D * ni * d * D);
+    Tensor HL = half_network(s, 0, 0, bl);
+    VO = keep(c, contract(c, HL, "scriSR", opT, "Ss", "crRi", F64, F64), vo_buf);
+    VI = keep(c, contract(c, HL, "scriSR", I, "Ss", "crRi", F64, F64), vi_buf);
+    c.arena.release(m2);
+  }
+  for (int x = 1; x <= L; ++x) {
+    const int z = (x % 2 == 0) ? 0 : 1;
+    const size_t m2 = c.arena.mark();
+    Tensor RO = contract(c, VO, "crRi", HR[z], "tircTR", "tT", F64, F64);
+    Tensor RI = contract(c, VI, "crRi", HR[z], "tircTR", "tT", F64, F64);
+    corr_finish(c, RO.d(), RI.d(), op, (int)d, out + (x - 1));
+    if (x < L) {
+      Tensor nO = absorb_column(s, c, VO, z);
+      Tensor nI = absorb_column(s, c, VI, z);
+      norm2(c, nI.d(), nI.numel(), nrm);
+      VO = keep(c, nO, vo_buf);
+      VI = keep(c, nI, vi_buf);
+      scale_by_inv(c, VO.d(), VO.numel(), nrm);
+      scale_by_inv(c, VI.d(), VI.numel(), nrm);
+    }
+    c.arena.release(m2);
+  }
   c.arena.release(mk);
 }
 
@@ -769,13 +950,20 @@ bool valid_cfg(const ctm_config* cfg) {
   if (cfg->d < 2 || cfg->D < 1 || cfg->chi < 1) return false;
   // the traced-boundary environment starts with bonds of dimension D^2
   if ((int64_t)cfg->chi < (int64_t)cfg->D * cfg->D) return false;
-  if (cfg->method != CTM_STANDARD && cfg->method != CTM_REDUCED) return false;
+  if (cfg->method != CTM_STANDARD && cfg->method != CTM_REDUCED && cfg->method != CTM_REDUCED_ENV)
+    return false;
   if (cfg->precision < CTM_FP64 || cfg->precision > CTM_BF16) return false;
   if (cfg->boot_iters < 0) return false;
+  // chi' and chi'' (0 = chi) may not be below chi: the second stages keep chi
+  if (cfg->chi_p < 0 || cfg->chi_pp < 0) return false;
+  if ((cfg->chi_p > 0 && cfg->chi_p < cfg->chi) || (cfg->chi_pp > 0 && cfg->chi_pp < cfg->chi))
+    return false;
   if (!(cfg->svd_cutoff >= 0.0) || cfg->svd_cutoff >= 1.0) return false;
   // every dimension product must stay well inside 32-bit GEMM sizes
   const double cap = std::max<double>(cfg->chi, (double)cfg->D * cfg->D);
   if (cap * cfg->D * cfg->D * cfg->D * cfg->d > 2.0e9) return false;
+  const double cpm = std::max<double>(std::max(cfg->chi_p, cfg->chi_pp), cfg->chi);
+  if (cpm * cfg->D * cfg->D * cfg->D * cfg->d * cfg->D > 4.0e10) return false;
   return true;
 }
 
@@ -783,6 +971,8 @@ void fill_from_cfg(ctm_solver* s, const ctm_config* cfg) {
   s->d = cfg->d;
   s->D = cfg->D;
   s->chi = cfg->chi;
+  s->chi_p = cfg->chi_p > 0 ? cfg->chi_p : cfg->chi;
+  s->chi_pp = cfg->chi_pp > 0 ? cfg->chi_pp : cfg->chi;
   s->method = cfg->method;
   s->precision = cfg->precision;
   s->boot_iters = cfg->boot_iters;
@@ -819,6 +1009,17 @@ size_t ctm_workspace_size(const ctm_config* cfg) {
     if (dbg) std::fprintf(stderr, "spectra peak %.1f MB\n", s.ctx.arena.peak / 1e6);
     for (int k = 0; k < 4; ++k) bond_energy(&s, k & 1, k >> 1, s.scal);
     if (dbg) std::fprintf(stderr, "energy peak %.1f MB\n", s.ctx.arena.peak / 1e6);
+    // observables: one-site expectations and a row correlation (its peak
+    // is reached at the first column; later columns reuse the same space)
+    {
+      const size_t mk = s.ctx.arena.mark();
+      double* dop = (double*)s.ctx.arena.alloc(sizeof(double) * s.d * s.d);
+      double* dout = (double*)s.ctx.arena.alloc(sizeof(double) * kMaxCorrLength);
+      expect1_impl(&s, dop, s.scal);
+      row_corr_impl(&s, dop, 2, dout);
+      s.ctx.arena.release(mk);
+    }
+    if (dbg) std::fprintf(stderr, "observables peak %.1f MB\n", s.ctx.arena.peak / 1e6);
     return s.ctx.arena.peak + 4096;
   } catch (...) {
     return 0;
@@ -954,6 +1155,63 @@ int ctm_read_delta(ctm_solver* s, double* delta) {
   const int st = status_from(s);
   if (st != CTM_OK) return st;
   return flag ? CTM_ENUMERIC : CTM_OK;
+}
+
+int ctm_expect1(ctm_solver* s, const double* op, double out[2]) {
+  if (!s || !op || !out) return CTM_EINVAL;
+  Ctx& c = s->ctx;
+  const int d = s->d;
+  double res[4];
+  int flag = 0;
+  try {
+    const size_t mk = c.arena.mark();
+    double* dop = (double*)c.arena.alloc(sizeof(double) * d * d);
+    c.check(hipMemcpyAsync(dop, op, sizeof(double) * d * d, hipMemcpyHostToDevice, c.stream));
+    expect1_impl(s, dop, s->scal + 48);
+    c.check(hipMemcpyAsync(res, s->scal + 48, sizeof(res), hipMemcpyDeviceToHost, c.stream));
+    c.check(hipMemcpyAsync(&flag, c.dev_flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    c.check(hipStreamSynchronize(c.stream));
+    c.arena.release(mk);
+  } catch (...) {
+    return fail_status(s);
+  }
+  const int st = status_from(s);
+  if (st != CTM_OK) return st;
+  bool bad = flag != 0;
+  for (int z = 0; z < 2; ++z) {
+    out[z] = res[2 * z] / res[2 * z + 1];
+    if (!std::isfinite(out[z])) bad = true;
+  }
+  return bad ? CTM_ENUMERIC : CTM_OK;
+}
+
+int ctm_row_correlation(ctm_solver* s, const double* op, int L, double* out) {
+  if (!s || !op || !out || L < 1 || L > kMaxCorrLength) return CTM_EINVAL;
+  Ctx& c = s->ctx;
+  const int d = s->d;
+  std::vector<double> res((size_t)L, 0.0);
+  int flag = 0;
+  try {
+    const size_t mk = c.arena.mark();
+    double* dop = (double*)c.arena.alloc(sizeof(double) * d * d);
+    double* dout = (double*)c.arena.alloc(sizeof(double) * L);
+    c.check(hipMemcpyAsync(dop, op, sizeof(double) * d * d, hipMemcpyHostToDevice, c.stream));
+    row_corr_impl(s, dop, L, dout);
+    c.check(hipMemcpyAsync(res.data(), dout, sizeof(double) * L, hipMemcpyDeviceToHost, c.stream));
+    c.check(hipMemcpyAsync(&flag, c.dev_flags, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+    c.check(hipStreamSynchronize(c.stream));
+    c.arena.release(mk);
+  } catch (...) {
+    return fail_status(s);
+  }
+  const int st = status_from(s);
+  if (st != CTM_OK) return st;
+  bool bad = flag != 0;
+  for (int x = 0; x < L; ++x) {
+    out[x] = res[x];
+    if (!std::isfinite(res[x])) bad = true;
+  }
+  return bad ? CTM_ENUMERIC : CTM_OK;
 }
 
 int ctm_energy(ctm_solver* s, const double* h2, double* e_site, double e_bond[4]) {

@@ -313,7 +313,79 @@ __global__ void rho_energy_kernel(const double* rho, const double* h4, int d, do
   out[1] = den;
 }
 
+// one-site: out[0] = sum rho[s,S] op[S,s], out[1] = sum rho[s,s]
+__global__ void rho1_expect_kernel(const double* rho, const double* op, int d, double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double num = 0.0, den = 0.0;
+  for (int s = 0; s < d; ++s) {
+    den += rho[s * d + s];
+    for (int S = 0; S < d; ++S) num += rho[s * d + S] * op[S * d + s];
+  }
+  out[0] = num;
+  out[1] = den;
+}
+
+// connected correlation from the right-end density matrices with op (RO)
+// and with the identity (RI) on the left site:
+// out = <op op> / <1 1> - (<op 1> / <1 1>) (<1 op> / <1 1>)
+__global__ void corr_finish_kernel(const double* RO, const double* RI, const double* op, int d,
+                                   double* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double oo = 0.0, oi = 0.0, io = 0.0, ii = 0.0;
+  for (int t = 0; t < d; ++t) {
+    oi += RO[t * d + t];
+    ii += RI[t * d + t];
+    for (int T = 0; T < d; ++T) {
+      oo += RO[t * d + T] * op[T * d + t];
+      io += RI[t * d + T] * op[T * d + t];
+    }
+  }
+  out[0] = oo / ii - (oi / ii) * (io / ii);
+}
+
+// guard regions (debug mode): a sentinel word everywhere, checked later
+constexpr uint64_t kGuardWord = 0xA5A5A5A5A5A5A5A5ull;
+
+__global__ __launch_bounds__(256) void guard_fill_kernel(uint64_t* p, int64_t n) {
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = kGuardWord;
+}
+
+__global__ __launch_bounds__(256) void guard_check_kernel(const uint64_t* p, int64_t n, int* flags) {
+  bool bad = false;
+  for (int64_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    bad |= p[i] != kGuardWord;
+  if (bad) atomicOr(flags, 4);
+}
+
 }  // namespace
+
+void guard_fill(Ctx& c, void* p, size_t bytes) {
+  if (c.dry || bytes < 8) return;
+  hipLaunchKernelGGL(guard_fill_kernel, dim3(64), dim3(256), 0, c.stream, (uint64_t*)p,
+                     (int64_t)(bytes / 8));
+  c.check_launch();
+}
+
+void guard_check(Ctx& c, const void* p, size_t bytes) {
+  if (c.dry || bytes < 8 || !c.dev_flags) return;
+  hipLaunchKernelGGL(guard_check_kernel, dim3(64), dim3(256), 0, c.stream, (const uint64_t*)p,
+                     (int64_t)(bytes / 8), c.dev_flags);
+  c.check_launch();
+}
+
+void rho1_expect(Ctx& c, const double* rho, const double* op, int d, double* out) {
+  if (c.dry) return;
+  hipLaunchKernelGGL(rho1_expect_kernel, dim3(1), dim3(64), 0, c.stream, rho, op, d, out);
+  c.check_launch();
+}
+
+void corr_finish(Ctx& c, const double* RO, const double* RI, const double* op, int d,
+                 double* out) {
+  if (c.dry) return;
+  hipLaunchKernelGGL(corr_finish_kernel, dim3(1), dim3(64), 0, c.stream, RO, RI, op, d, out);
+  c.check_launch();
+}
 
 Tensor make_view(void* p, int dt, std::initializer_list<int64_t> dims) {
   Tensor t;

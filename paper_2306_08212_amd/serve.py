@@ -210,8 +210,10 @@ class Server:
     if None); max_slots: solves admitted at once.
     """
 
-    def __init__(self, backend, budget_bytes: Optional[int] = None, max_slots: int = 16):
+    def __init__(self, backend, budget_bytes: Optional[int] = None, max_slots: int = 16,
+                 on_result=None):
         self.b = backend
+        self.on_result = on_result     # called with each Result as it completes
         self.budget = int(budget_bytes if budget_bytes is not None
                           else 0.8 * backend.free_bytes())
         self.max_slots = max_slots
@@ -266,6 +268,8 @@ class Server:
                 env = self.b.final_env(a.handle)
         self.results.append(Result(a.req.id, a.req.D, a.req.chi, a.req.t_arrival, a.t_admit,
                                    self.b.now(), a.iters, a.delta, e, eb, status, env))
+        if self.on_result is not None:
+            self.on_result(self.results[-1])
         self.b.release(a.handle)
         self.used -= a.nbytes
         self.active.remove(a)

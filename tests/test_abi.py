@@ -48,7 +48,9 @@ def test_workspace_size_validation(lib):
            P.Config(precision=3), P.Config(boot_iters=-1), P.Config(svd_cutoff=-1.0),
            P.Config(svd_cutoff=1.0),
            # chi below D^2: the initial traced-boundary bonds would not fit
-           P.Config(D=3, chi=8), P.Config(D=2, chi=3), P.Config(D=8, chi=63)]
+           P.Config(D=3, chi=8), P.Config(D=2, chi=3), P.Config(D=8, chi=63),
+           # chi' and chi'' below chi (0 means chi)
+           P.Config(chi=8, chi_p=4), P.Config(chi=8, chi_pp=7), P.Config(chi_p=-1)]
     for cfg in bad:
         c = cfg.to_c()
         assert lib.ctm_workspace_size(ctypes.byref(c)) == 0, cfg
@@ -60,6 +62,9 @@ def test_workspace_size_grows_with_sizes(lib):
              [(2, 4), (2, 8), (2, 16), (3, 9), (3, 36), (4, 64)]]
     assert sizes[0] < sizes[1] < sizes[2]
     assert sizes[3] < sizes[4] < sizes[5]
+    # a larger chi' or chi'' needs more workspace
+    assert P.workspace_size(P.Config(D=3, chi=18, chi_p=36)) > P.workspace_size(P.Config(D=3, chi=18))
+    assert P.workspace_size(P.Config(D=3, chi=18, chi_pp=36)) > P.workspace_size(P.Config(D=3, chi=18))
     # FP32 / BF16 chains never need more than FP64
     for prec in (P.FP32, P.BF16):
         assert P.workspace_size(P.Config(D=4, chi=64, precision=prec)) <= \

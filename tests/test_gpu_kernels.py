@@ -153,21 +153,54 @@ def test_tsvd_matches_oracle_truncate(name, make, k):
     assert abs(np.sum(R * R) - np.clip(lam[int(keep.sum()):], 0, None).sum()) < 1e-10 * lam[0]
 
 
-@pytest.mark.parametrize("m,n,k", [(1100, 1200, 128), (2048, 2048, 256)])
-def test_tsvd_randomized_range(m, n, k):
-    """Large problems go through the randomised range finder (one power
-    iteration, k + max(32, k/4) columns): the top half of the spectrum to
-    1e-12, the truncation residual within 1e-6 of the optimum, U orthonormal."""
-    log("tsvd randomized", m, n, k)
-    M = _graded(m, n, 0.9 ** (256.0 / k), 11)
-    U, S = tsvd(M, k)
-    s = np.linalg.svd(M, compute_uv=False)
-    h = k // 2
-    np.testing.assert_allclose(S[:h], s[:h], rtol=0, atol=1e-12 * s[0])
-    np.testing.assert_allclose(U.T @ U, np.eye(k), atol=1e-12)
+def _move_spectrum(D, chi, col):
+    """Singular values of a truncation input of the move (column 0: the side
+    product L = C1 T1, column 1: the row M'), written by the oracle into
+    tests/golden/spectra_D<D>_chi<chi>.txt."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", f"spectra_D{D}_chi{chi}.txt")
+    return np.loadtxt(path)[:, col]
+
+
+@pytest.mark.parametrize("D,chi,col", [(6, 144, 0), (6, 144, 1), (8, 256, 0), (8, 256, 1)])
+def test_tsvd_full_size_move_spectra(D, chi, col):
+    """The large truncations of the move ((chi D) x (D chi) to chi: 864 x 864
+    to 144 and 2048 x 2048 to 256) go through the randomised range finder.
+    On matrices with the singular values of the move's own inputs (side
+    product L and row M', from the oracle) and random singular vectors, the
+    result is the exact truncation to rounding, compared with the oracle's
+    LAPACK-based truncate: every kept singular value to 1e-13 sigma_0, every
+    singular vector whose value is separated from its neighbours by more
+    than 1e-6 sigma_0 element-wise, the kept projector applied to M to
+    1e-11 ||M||, the Eckart-Young residual at its optimum to 1e-10
+    (relative), and U orthonormal."""
+    s = _move_spectrum(D, chi, col)
+    n = s.size
+    log("tsvd full size", D, chi, "L" if col == 0 else "M'", n)
+    M = (random_orthogonal(n, 40 + col) * s) @ random_orthogonal(n, 50 + col).T
+    U, S = tsvd(M, chi)
+    Uo, So = O.truncate(M, chi)
+    s0 = So[0]
+    keep = So > 0
+    # a value within rounding of the cutoff tau sigma_0 may be kept on one side only
+    near_cut = np.abs(So - 1e-14 * s0) < 1e-15 * s0
+    assert np.array_equal((S > 0)[~near_cut], keep[~near_cut])
+    np.testing.assert_allclose(S, So, rtol=0, atol=1e-13 * s0)
+    sp = np.concatenate([[np.inf], So, [0.0]])
+    checked = 0
+    for c in np.nonzero(keep)[0]:
+        gap = min(sp[c] - sp[c + 1], sp[c + 1] - sp[c + 2]) / s0
+        if gap > 1e-6:
+            np.testing.assert_allclose(U[:, c], Uo[:, c], rtol=0, atol=2e-12 / gap + 1e-11)
+            checked += 1
+    assert checked >= 5
+    kk = keep & (S > 0)
+    Pd = U[:, kk] @ (U[:, kk].T @ M) - Uo[:, kk] @ (Uo[:, kk].T @ M)
+    assert np.linalg.norm(Pd) <= 1e-11 * np.linalg.norm(M)
     R = M - U @ (U.T @ M)
-    opt = np.sum(s[k:] ** 2)
-    assert np.sum(R * R) <= opt * (1 + 1e-6) + 1e-24 * s[0] ** 2
+    opt = np.sum(np.linalg.svd(M, compute_uv=False)[int(keep.sum()):] ** 2)
+    assert np.sum(R * R) <= opt * (1.0 + 1e-10) + (1e-13 * s0) ** 2
+    np.testing.assert_allclose(U[:, kk].T @ U[:, kk], np.eye(int(kk.sum())), atol=1e-12)
 
 
 def test_tsvd_tall_compressed_matches_oracle():

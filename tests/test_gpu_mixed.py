@@ -1,5 +1,6 @@
 """Mixed precision: absorption chains on FP32 / BF16 MFMA (FP32 accumulation),
-truncation SVDs, norms and energies in FP64.
+truncation SVDs, norms and energies in FP64; and full-size FP64 / FP32
+parity with the oracle's stored results.
 
 The per-move precision error is measured from one shared FP64 state: the
 same move is applied once in FP64 and once in FP32 (or BF16), with identical
@@ -71,28 +72,72 @@ def test_headline_fp32_energy_within_1e6():
     assert err[P.FP32] < 1e-6
 
 
-def test_config3_report_against_oracle():
-    """d=2, D=6, chi=144: two iterations in FP64, FP32 and BF16, reported
-    against the oracle's energies (tests/golden/config3_oracle.json, written
-    by make_config3.py from the oracle alone).  The truncations at this size
-    go through the randomised range finder, and the reduced move's
-    sensitivity applies, so the check is a band, printed in full."""
-    path = os.path.join(GOLDEN, "config3_oracle.json")
-    if not os.path.exists(path):
-        pytest.skip("config3_oracle.json not generated")
-    ref = json.load(open(path))
-    A, B = site_tensors(2, 6, 0)
-    rows = []
+def _golden(D, chi):
+    """The oracle's energies at (D, chi) after one iteration and after one
+    more left move (make_config4.py), and the spread between its gesdd and
+    gesvd runs: the largest difference, relative to |e_site|, of any energy
+    -- how far rounding alone moves the oracle's own results here."""
+    base = os.path.join(GOLDEN, f"config_D{D}_chi{chi}_oracle")
+    ref = json.load(open(base + ".json"))["results"]
+    # the gesvd variant, or where that is too slow to produce (D = 8) the
+    # variant with one ulp of noise on every truncated matrix; the noise is
+    # a smaller backward error than two different SVD routines make, so
+    # its spread counts ten times more
+    if os.path.exists(base + "_gesvd.json"):
+        alt, factor = json.load(open(base + "_gesvd.json"))["results"], 1.0
+    else:
+        alt, factor = json.load(open(base + "_noise.json"))["results"], 10.0
+    spread = 0.0
+    for key in ref:
+        e = abs(ref[key]["e_site"])
+        vals = [ref[key]["e_site"]] + ref[key]["e_bond"]
+        avals = [alt[key]["e_site"]] + alt[key]["e_bond"]
+        spread = max(spread, factor * max(abs(a - b) for a, b in zip(vals, avals)) / e)
+    return ref, spread
+
+
+def _full_size_run(D, chi, prec):
+    A, B = site_tensors(2, D, 0)
+    s = P.Solver(P.Config(d=2, D=D, chi=chi, method=P.REDUCED, precision=prec), A, B)
+    out = {}
+    s.iterate(1)
+    out["iteration1"] = s.energy()
+    s.move(P.LEFT)
+    out["iteration1_left"] = s.energy()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("D,chi", [(6, 144), (8, 256)])
+def test_full_size_against_oracle(D, chi):
+    """d=2, D=6, chi=144 and D=8, chi=256 (the headline size), seed 0: one
+    CTM iteration (the bootstrap) and one more reduced left move, every
+    energy against the FP64 oracle's (tests/golden, written by
+    make_config4.py from the oracle alone).
+
+    FP64: within max(1e-10, 10 x spread) relative, where the spread is how
+    far the oracle itself moves when its SVD driver changes (gesdd ->
+    gesvd; at D=8 ten times the move under one ulp of noise on every
+    truncated matrix): the truncations keep directions whose singular values sit at
+    1e-11 .. 1e-17 of the largest, which any backward-stable SVD fixes only
+    to eps / gap, so no implementation is determined more closely than
+    that.  FP32 chains: per-site energy within 1e-6 (relative) of the
+    oracle, the mixed-precision contract.  BF16: reported, with a 5e-2 band."""
+    ref, spread = _golden(D, chi)
+    bar64 = max(1e-10, 10.0 * spread)
+    log(f"D={D} chi={chi}: oracle gesdd/gesvd spread {spread:.2e} -> FP64 bar {bar64:.2e}")
     for prec, name in ((P.FP64, "fp64"), (P.FP32, "fp32"), (P.BF16, "bf16")):
-        s = P.Solver(P.Config(d=2, D=6, chi=144, method=P.REDUCED, precision=prec), A, B)
-        for it in (1, 2):
-            s.iterate(1)
-            e, eb = s.energy()
-            eo = ref["iterations"][str(it)]["e_site"]
-            rows.append((name, it, e, abs(e - eo) / abs(eo)))
-        s.close()
-    for r in rows:
-        log("config3 %s iteration %d e_site %.12f rel err vs oracle %.2e" % r)
-    for name, it, e, rel in rows:
-        assert np.isfinite(e)
-        assert rel < (1e-3 if name != "bf16" else 5e-2)
+        got = _full_size_run(D, chi, prec)
+        for key in ("iteration1", "iteration1_left"):
+            e, eb = got[key]
+            eo, ebo = ref[key]["e_site"], ref[key]["e_bond"]
+            rel = abs(e - eo) / abs(eo)
+            relb = max(abs(a - b) for a, b in zip(eb, ebo)) / abs(eo)
+            log(f"  {name} {key}: e_site {e:.15f} oracle {eo:.15f} rel err {rel:.2e} bonds {relb:.2e}")
+            assert np.isfinite(e)
+            if prec == P.FP64:
+                assert rel <= bar64 and relb <= bar64
+            elif prec == P.FP32:
+                assert rel <= 1e-6
+            else:
+                assert rel <= 5e-2

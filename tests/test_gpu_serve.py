@@ -89,3 +89,84 @@ def test_warm_started_request_matches_oracle():
     cold = Server(GpuBackend(), budget_bytes=2 ** 30, max_slots=1).run(
         [Request(**{**req.__dict__, "env": None})])[0]
     assert abs(cold.e_site - res.e_site) > 1e-12
+
+
+@pytest.mark.parametrize("D,chi,prec", [(3, 31, 1), (3, 17, 0), (4, 40, 1)])
+def test_results_do_not_depend_on_workspace_contents(D, chi, prec):
+    """The same solve on a workspace holding zeros, NaN bit patterns or
+    random bytes gives bitwise the same energies: no kernel reads memory
+    that the solve has not written (a solve in the serving mix gets memory
+    another solve used before)."""
+    import torch
+    import paper_2306_08212_amd as P
+    A, B = site_tensors(2, D, 4)
+    cfg = P.Config(d=2, D=D, chi=chi, method=P.REDUCED, precision=prec)
+    n = P.workspace_size(cfg)
+    out = []
+    for fill in ("zero", "nan", "random"):
+        if fill == "zero":
+            ws = torch.zeros(n, dtype=torch.uint8, device="cuda")
+        elif fill == "nan":
+            ws = torch.full((n,), 0xFF, dtype=torch.uint8, device="cuda")
+        else:
+            g = torch.Generator(device="cuda")
+            g.manual_seed(5)
+            ws = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda", generator=g)
+        torch.cuda.synchronize()
+        s = P.Solver(cfg, A, B, workspace=ws)
+        s.iterate(2)
+        e, eb = s.energy()
+        s.close()
+        log(f"D={D} chi={chi} prec={prec} workspace {fill}: {e!r}")
+        out.append((e, eb))
+    assert out[0] == out[1] == out[2]
+
+
+@pytest.mark.parametrize("D,chi,prec,method", [(3, 31, 1, 1), (8, 65, 1, 1), (6, 120, 1, 1),
+                                               (4, 40, 0, 2), (3, 17, 2, 0)])
+def test_no_write_past_the_workspace(D, chi, prec, method):
+    """A solve (iterations, energy, observables) writes nothing beyond the
+    workspace it was given: a guard region after it, filled with a
+    sentinel, is unchanged afterwards.  (Solves of the serving mix sit next
+    to each other in device memory.)"""
+    import torch
+    import paper_2306_08212_amd as P
+    A, B = site_tensors(2, D, 3)
+    cfg = P.Config(d=2, D=D, chi=chi, method=method, precision=prec)
+    n = P.workspace_size(cfg)
+    guard = 1 << 22
+    buf = torch.full((n + guard,), 0xA5, dtype=torch.uint8, device="cuda")
+    s = P.Solver(cfg, A, B, workspace=buf[:n])
+    s.iterate(3)
+    s.energy()
+    sz = np.array([[0.5, 0.0], [0.0, -0.5]])
+    s.expect1(sz)
+    s.row_correlation(sz, 3)
+    s.close()
+    torch.cuda.synchronize()
+    tail = buf[n:]
+    bad = int((tail != 0xA5).sum().item())
+    log(f"D={D} chi={chi} prec={prec} method={method}: workspace {n / 1e6:.1f} MB, "
+        f"{bad} guard bytes changed")
+    assert bad == 0
+
+
+@pytest.mark.parametrize("D,chi,prec,method", [(3, 31, 1, 1), (6, 120, 1, 1), (8, 65, 1, 1),
+                                               (4, 40, 0, 2), (3, 17, 2, 0)])
+def test_branches_stay_inside_their_workspace_slices(D, chi, prec, method, monkeypatch):
+    """The concurrent branches of a move each get a slice of the workspace.
+    With CTM_DEBUG_GUARD set, every slice is followed by a sentinel region
+    that is checked after the branches join (a write past a slice would land
+    in the next branch's memory, and the result would then depend on the
+    order the branches run in); a changed byte makes the next synchronising
+    call fail with CTM_ENUMERIC.  Four iterations, so graph-replayed moves
+    are included."""
+    import paper_2306_08212_amd as P
+    monkeypatch.setenv("CTM_DEBUG_GUARD", "1")
+    A, B = site_tensors(2, D, 3)
+    s = P.Solver(P.Config(d=2, D=D, chi=chi, method=method, precision=prec), A, B)
+    s.iterate(4)
+    e, _ = s.energy()
+    s.close()
+    log(f"guarded branches D={D} chi={chi} prec={prec} method={method}: e_site {e!r}")
+    assert np.isfinite(e)
