@@ -32,18 +32,33 @@ PEAK = {"gemm_f64": (78.6e12, "TFLOP/s", "mfma"), "gemm_f32": (157.3e12, "TFLOP/
 KERNEL_OF = {"gemm_f64": "gemm_f64_kernel", "gemm_f32": "gemm_f32_kernel",
              "gemm_bf16": "gemm_bf16_kernel", "permute": "permute_ctile_kernel/permute_rows_kernel",
              "svd_round": "jac_round_kernel", "chol": "chol_block_kernel"}
-# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE (KiB per
-# dispatch) at this workload, scaled by the readings for a plain 64 MiB copy
-# (FETCH_SIZE reads half of the bytes moved, WRITE_SIZE all of them):
-# profiles/hbm_counters_reduced_move_D8_chi256.md.  Only for kernels whose
-# code is the one the counters were taken on.
-TRAFFIC = {"chol_block_kernel": 1024.0 * (2.0 * 28.019 + 32.186),
-           "jac_round_kernel": 1024.0 * (2.0 * 306.009 + 174.886)}
+# HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, for a
+# kernel whose code is the one the counters were taken on; none is listed
+# for the current kernels (the roofline's traffic is then null).
+TRAFFIC = {}
 MOVE_ORDER = (0, 2, 1, 3)     # left, right, up, down
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def _roctx():
+    """roctxProfilerResume / roctxProfilerPause of the ROCm profiler SDK:
+    under `rocprofv3 --selected-regions` they bracket what is recorded (the
+    profiled pass, so the trace holds the launches whose durations the HIP
+    events measure); otherwise they do nothing.  None when the library is
+    absent."""
+    import ctypes
+    for name in ("librocprofiler-sdk-roctx.so.1", "/opt/rocm/lib/librocprofiler-sdk-roctx.so.1"):
+        try:
+            lib = ctypes.CDLL(name)
+            lib.roctxProfilerResume.argtypes = [ctypes.c_uint64]
+            lib.roctxProfilerPause.argtypes = [ctypes.c_uint64]
+            return lib
+        except (OSError, AttributeError):
+            continue
+    return None
 
 
 def f_move(d, D, chi):
@@ -218,12 +233,14 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=4,
                     help="moves timed again with FP64 chains (0 = skip)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--serve-requests", type=int, default=32,
+    ap.add_argument("--serve-requests", type=int, default=16,
                     help="requests in each serving stream (the full serving workload is "
                          "512; 0 = skip serving)")
     ap.add_argument("--serve-dmax", type=int, default=8,
                     help="largest D in the serving stream (D uniform in 3..dmax)")
-    ap.add_argument("--serve-iters", type=int, default=30, help="iteration cap per solve")
+    ap.add_argument("--serve-iters", type=int, default=10,
+                    help="iteration cap per solve (the serving workload's own cap is 30; "
+                         "10 keeps the default run to a few minutes)")
     ap.add_argument("--serve-tol", type=float, default=1e-6, help="delta that ends a solve")
     ap.add_argument("--no-methods", action="store_true",
                     help="skip the standard / reduced-env / sequential comparison")
@@ -322,11 +339,16 @@ def main():
         """Wall time of nmoves moves (torch events around the launches, the
         device synchronised on both sides).  With profile=True every kernel
         launch is also bracketed by HIP events on the stream it runs on, for
-        the per-class durations; that adds host work per launch, so the
+        the per-class durations, with a short gate kernel ahead of each start
+        event (so the interval is the kernel's own duration, not the time
+        the host takes to issue it); the moves then run eagerly, so the
         headline number comes from an unprofiled pass."""
         torch.cuda.synchronize()
+        rt = _roctx() if profile else None
         if profile:
             s.profile(True)
+            if rt is not None:
+                rt.roctxProfilerResume(0)
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -338,6 +360,8 @@ def main():
         ms = ev0.elapsed_time(ev1)
         prof = None
         if profile:
+            if rt is not None:
+                rt.roctxProfilerPause(0)
             prof = s.profile_read()
             s.profile(False)
         log(f"bench: {tag}{' (profiled)' if profile else ''}: {nmoves} moves in {ms:.1f} ms")
@@ -346,7 +370,7 @@ def main():
     ms, _ = timed(args.steps, args.precision)
     moves_per_s = args.steps / (ms / 1e3)
     nprof = max(1, min(args.steps, 4))
-    ms_prof, prof = timed(nprof, args.precision, profile=True)
+    _, prof = timed(nprof, args.precision, profile=True)
 
     # dominant kernel by summed duration, among the classes that are one kernel
     dom = max((k for k in prof if k in PEAK), key=lambda k: prof[k][1])
@@ -359,10 +383,12 @@ def main():
         achieved = kby / (kms / 1e3) / 1e9
         peak_u = peak / 1e9
     fm = f_move(d, D, chi)
-    # per-class kernel time summed over all streams (the classes overlap in
-    # time, so shares can add up to more than 1)
+    # per-class kernel time summed over all streams; share = fraction of the
+    # summed kernel time of the profiled moves (the profiled pass itself is
+    # stretched by the gate kernels, so its wall time is not the reference)
+    total_k = sum(v[1] for v in prof.values())
     breakdown = {k: {"launches": v[0] / nprof, "ms_per_move": v[1] / nprof,
-                     "share": v[1] / ms_prof if ms_prof > 0 else 0.0}
+                     "share": v[1] / total_k if total_k > 0 else 0.0}
                  for k, v in prof.items() if v[0]}
     # achieved rates of the classes with an algorithmic count: matrix-core
     # GEMMs in TFLOP/s (fraction of their dtype's dense peak), memory-bound
@@ -384,7 +410,6 @@ def main():
     # the absorption chains (FP32 / BF16 GEMMs and permutes), as shares of
     # the summed kernel time of a move
     trunc_cls = ("gemm_f64", "svd_round", "svd_other", "chol", "reduce")
-    total_k = sum(v[1] for v in prof.values())
     trunc_share = sum(prof[k][1] for k in trunc_cls if k in prof) / total_k if total_k else None
 
     fp64_mps = None

@@ -2,6 +2,7 @@
 // the workspace arena, and the launch wrappers of every kernel.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
@@ -104,29 +105,53 @@ struct Ctx {
   Tensor alloc(int dt, const std::vector<int64_t>& dims);
 };
 
+// Launches a kernel that holds the stream for ~40 us (profiling only).
+void prof_gate(hipStream_t stream);
+
 // Records one launch (or a short sequence counted as `launches` launches of
-// class cls) when profiling is on.
+// class cls) when profiling is on.  Two ways of timing:
+// * a single kernel launched through launch(ps, ...) below carries the two
+//   events in its own dispatch (hipExtLaunchKernelGGL), so they read the
+//   kernel's start and end, the interval a kernel tracer reports;
+// * otherwise HIP events are recorded on the stream around the scope, with a
+//   gate kernel ahead of the start event that lets the host enqueue the
+//   events and the launches before the stream reaches them (the interval
+//   then holds the kernels and the event markers, not host issue time).
 struct ProfScope {
   Ctx& c;
   int cls;
   double flops, bytes;
   int launches;
+  bool ext;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  ProfScope(Ctx& cx, int k, double f, double b, int nl = 1)
-      : c(cx), cls(k), flops(f), bytes(b), launches(nl) {
+  ProfScope(Ctx& cx, int k, double f, double b, int nl = 1, bool ext_launch = false)
+      : c(cx), cls(k), flops(f), bytes(b), launches(nl), ext(ext_launch) {
     if (c.prof && !c.dry) {
       c.check(hipEventCreate(&e0));
       c.check(hipEventCreate(&e1));
-      c.check(hipEventRecord(e0, c.stream));
+      if (!ext) {
+        prof_gate(c.stream);
+        c.check(hipEventRecord(e0, c.stream));
+      }
     }
   }
   ~ProfScope() {
     if (c.prof && !c.dry && e0) {
-      c.check(hipEventRecord(e1, c.stream));
+      if (!ext) c.check(hipEventRecord(e1, c.stream));
       c.prof->recs.push_back({cls, flops, bytes, e0, e1, launches});
     }
   }
 };
+
+// One kernel launch on `stream`; under a profiling scope made with
+// ext_launch = true the scope's events ride on the dispatch.
+template <typename F, typename... Args>
+void launch(ProfScope& ps, F kernel, dim3 grid, dim3 block, hipStream_t stream, Args... args) {
+  if (ps.ext && ps.e0 != nullptr)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, stream, ps.e0, ps.e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, stream, args...);
+}
 
 // ---------------------------------------------------------------- kernels
 

@@ -343,33 +343,35 @@ void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A, i
     {
       ProfScope ps(c, K_GEMM_F64, 2.0 * m * n * (double)k * batch,
                    ((double)m * k + (double)k * n) * es * batch +
-                       (double)m * n * eo * batch * splits);
-      hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, c.stream, m, n, k, alpha,
+                       (double)m * n * eo * batch * splits, 1, true);
+      launch(ps, gemm_f64_kernel, grid, dim3(256), c.stream, m, n, k, alpha,
                          (const double*)A, lda, ta, (const double*)B, ldb, tb, beta, (double*)C,
                          ldc, sA, sB, sC, tn, kchunk, part);
     }
     if (splits > 1) {
       ProfScope ps(c, K_REDUCE, (double)m * n * batch * splits,
-                   (double)m * n * batch * 8.0 * (splits + 1));
+                   (double)m * n * batch * 8.0 * (splits + 1), 1, true);
       int64_t blocks = ((int64_t)m * n * batch + 255) / 256;
       if (blocks > 4096) blocks = 4096;
-      hipLaunchKernelGGL(gemm_f64_splitk_sum, dim3((unsigned)blocks), dim3(256), 0, c.stream, m, n,
+      launch(ps, gemm_f64_splitk_sum, dim3((unsigned)blocks), dim3(256), c.stream, m, n,
                          batch, splits, alpha, part, beta, (double*)C, ldc, sC);
     }
   } else if (dtype == F32) {
     ProfScope ps(c, K_GEMM_F32, 2.0 * m * n * (double)k * batch,
-                 ((double)m * k + (double)k * n) * es * batch + (double)m * n * eo * batch);
+                 ((double)m * k + (double)k * n) * es * batch + (double)m * n * eo * batch, 1,
+                 true);
     const int tm = (m + F32_BM - 1) / F32_BM, tn = (n + F32_BN - 1) / F32_BN;
     dim3 grid(tm * tn, batch);
-    hipLaunchKernelGGL(gemm_f32_kernel, grid, dim3(256), 0, c.stream, m, n, k, (float)alpha,
+    launch(ps, gemm_f32_kernel, grid, dim3(256), c.stream, m, n, k, (float)alpha,
                        (const float*)A, lda, ta, (const float*)B, ldb, tb, (float)beta,
                        (float*)C, ldc, sA, sB, sC, tn);
   } else {
     ProfScope ps(c, K_GEMM_BF16, 2.0 * m * n * (double)k * batch,
-                 ((double)m * k + (double)k * n) * es * batch + (double)m * n * eo * batch);
+                 ((double)m * k + (double)k * n) * es * batch + (double)m * n * eo * batch, 1,
+                 true);
     const int tm = (m + B16_BM - 1) / B16_BM, tn = (n + B16_BN - 1) / B16_BN;
     dim3 grid(tm * tn, batch);
-    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, c.stream, m, n, k, (float)alpha,
+    launch(ps, gemm_bf16_kernel, grid, dim3(256), c.stream, m, n, k, (float)alpha,
                        (const __bf16*)A, lda, ta, (const __bf16*)B, ldb, tb, (float)beta,
                        (float*)C, ldc, sA, sB, sC, tn);
   }

@@ -85,6 +85,22 @@ __device__ __forceinline__ double rsq_nr(double x) {
   return y;
 }
 
+// Orders a wave's LDS accesses for the compiler across this point (the
+// hardware completes one wave's LDS operations in order).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lane `lane`'s value of v (lane a compile-time or wave-uniform index).
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Rotation test for a column pair (see the file comment): thr = 4 eps ||M||_F.
 // Compared in squares (Gram entries of normalised data are far from overflow).
 __device__ __forceinline__ bool needs_rotation(double app, double aqq, double apq, double tol,
@@ -640,203 +656,247 @@ __global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restric
 // columns of A (R is invertible on the live columns) and is orthonormal only
 // up to about shift kappa^2, which is all a power-iteration basis needs.
 //
-// Layout for latency (every step of the factorisation is on the critical
-// path of the orthonormalisation): thread t keeps the 4 x 4 entries (t/16 +
-// 16 a, t%16 + 16 b) of the trailing matrix in registers for the whole
-// factorisation; a step reads the published pivot row from LDS, applies the
-// rank-1 update to its tile and the owners publish the next row, one barrier
-// per step.  The acceptance tests read the recorded pivots after the loop.
-// R^{-1} is formed by 16 x 16 blocks: the diagonal blocks by back
-// substitution, a column per thread, then the blocks above the diagonal by
-// block back substitution, three levels of small products.
-__global__ __launch_bounds__(256) void chol_block_kernel(const double* __restrict__ G, int nb,
-                                                   int c0, const double* __restrict__ nrm0,
-                                                   int* __restrict__ dead, int final,
-                                                   double* __restrict__ Ri,
-                                                   int* __restrict__ healthy, double shift,
-                                                   double dead_tol) {
+// One wave does everything, in registers, with no workgroup barrier (a
+// wave's LDS operations complete in order, and the fences below only keep
+// the compiler from moving LDS accesses across a step):
+// * Factorisation: lane i holds row i of the trailing matrix (rows and
+//   columns beyond nb are zero and give zero pivots).  Row j (lane k's
+//   element j, equal to row j by symmetry) goes through LDS as Rw[j], and
+//   each lane applies w_ik -= (w_ij / d_j) Rw[j][k] for k > j.  The serial
+//   path is the chain of pivots: d_{j+1} = a - Rw[j][j+1]^2 / d_j with a the
+//   element (j+1, j+1) before step j, formed as one FMA from values that
+//   are ready earlier, then its reciprocal (hardware estimate and one cubic
+//   Newton step, three FMAs).  Those FMAs sit between four groups of the
+//   step's updates so their latencies overlap them, and each group's entries
+//   of the next pivot row are loaded as soon as the group is done.
+//   The unscaled rows Rw[j] and the pivots are kept; R[j][k] = Rw[j][k] /
+//   sqrt(d_j).
+// * Acceptance on the recorded pivots, then R^{-1} by forward substitution
+//   on L = R^T: lane i forms row i of R^{-1} (y = L^{-1} e_i), reading the
+//   rows of Rw (the columns of L) in order.  The serial path is two FMAs per
+//   step (the next accumulator, then the next scaled unknown, formed before
+//   the step's other updates).
+// The loops are unrolled so every per-lane array stays in registers.
+__device__ __forceinline__ double rcp_cubic(double x, double y0) {
+  const double e = fma(-x, y0, 1.0);
+  return fma(y0, fma(e, e, e), y0);
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_block_kernel(
+    const double* __restrict__ G, int nb, int c0, const double* __restrict__ nrm0,
+    int* __restrict__ dead, int final, double* __restrict__ Ri, int* __restrict__ healthy,
+    double shift, double dead_tol) {
   __shared__ double Rw[OBW][OBP];   // row j of the trailing matrix as it stood at step j
-  __shared__ double X[OBW][OBP];    // R^{-1}
-  __shared__ double gd[OBW], sgd[OBW], n0[OBW], rinv[OBW];
-  __shared__ int isdead[OBW];
-  __shared__ int ok_s;
-  const int t = threadIdx.x;
-  const int ti = t >> 4, tk = t & 15;   // tile: rows ti + 16 a, columns tk + 16 b
-  double w[4][4];
+  __shared__ double Gs[OBW][OBP];   // G, staged with coalesced loads
+  const int i = threadIdx.x;
+  {
+    // clamped addresses: every load is issued, out-of-range values dropped
+    const int ic = i < nb ? i : nb - 1;
+    double g[OBW];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+    for (int r = 0; r < OBW; ++r) g[r] = G[(r < nb ? r : nb - 1) * nb + ic];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int i = ti + 16 * a, k = tk + 16 * b;
-      w[a][b] = (i < nb && k < nb) ? G[i * nb + k] * (i == k ? 1.0 + shift : 1.0) : 0.0;
-    }
-  for (int e = t; e < OBW * OBW; e += 256) Rw[e >> 6][e & 63] = 0.0;
-  if (t < OBW) {
-    gd[t] = t < nb ? G[t * nb + t] : 0.0;
-    sgd[t] = sqrt(gd[t]);
-    n0[t] = t < nb ? nrm0[c0 + t] : 0.0;
-    rinv[t] = 0.0;
+    for (int r = 0; r < OBW; ++r) Gs[r][i] = (r < nb && i < nb) ? g[r] : 0.0;
   }
-  __syncthreads();
-  if (ti == 0)
+  const double gii = i < nb ? G[i * nb + i] : 0.0;
+  const double n0 = i < nb ? nrm0[c0 + i] : 0.0;
+  wave_lds_sync();
+
+  double w[OBW], row[OBW];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) Rw[0][tk + 16 * b] = w[0][b];
-  __syncthreads();
-  // the pivots are recorded and the acceptance tests run after the loop, so
-  // a step is the pivot's rsqrt, the rank-1 update of the thread's tile and
-  // the publication of the next row
-  __shared__ double pd[OBW];
-  for (int j = 0; j < nb; ++j) {
-    const double d = Rw[j][j];
-    const double inv = (d > 0.0 && gd[j] != 0.0) ? rsq_nr(d) : 0.0;
-    if (t == 0) {
-      rinv[j] = inv;
-      pd[j] = d;
-    }
-    // row j of the factor, masked to the trailing columns by a multiply (the
-    // loads are unconditional: every entry of Rw is finite)
-    double ri[4], rk[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      const int i = ti + 16 * a, k = tk + 16 * a;
-      ri[a] = Rw[j][i] * (i > j ? inv : 0.0);
-      rk[a] = Rw[j][k] * (k > j ? inv : 0.0);
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) w[a][b] = fma(-ri[a], rk[b], w[a][b]);
-    // the owners of row j + 1 publish it for the next step
-    const int jn = j + 1, an = jn >> 4;
-    if (jn < nb && ti == (jn & 15))
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const double v = an == 0 ? w[0][b] : (an == 1 ? w[1][b] : (an == 2 ? w[2][b] : w[3][b]));
-        Rw[jn][tk + 16 * b] = v;
-      }
-    __syncthreads();
+  for (int k = 0; k < OBW; ++k) {
+    w[k] = Gs[i][k] * (i == k ? 1.0 + shift : 1.0);
+    row[k] = 0.0;
   }
+  // columns with G_jj != 0, one bit per lane
+  const unsigned long long gmask = __ballot(gii != 0.0);
+  Rw[0][i] = w[0];
+  wave_lds_sync();
+#pragma unroll
+  for (int k = 1; k < OBW; ++k) row[k] = Rw[0][k];
+  double d = readlane_f64(w[0], 0);
+  bool live = d > 0.0 && (gmask & 1ull);
+  double rc = rcp_cubic(d, __builtin_amdgcn_rcp(d));   // used only when live
+  double a = readlane_f64(w[1], 1);                   // element (1, 1) before step 0
+  double my_d = i == 0 ? d : 0.0;
+#pragma clang loop unroll(full)
+  for (int j = 0; j < OBW; ++j) {
+    const double ci = live ? w[j] * rc : 0.0;
+    double dn = 0.0, y = 1.0;
+    bool liven = false;
+    if (j + 1 < OBW) {
+      // next pivot: lane j + 1's own update of its element j + 1
+      dn = fma(-(row[j + 1] * (live ? rc : 0.0)), row[j + 1], a);
+      liven = dn > 0.0 && ((gmask >> (j + 1)) & 1ull);
+      my_d = i == j + 1 ? dn : my_d;
+      y = __builtin_amdgcn_rcp(dn);
+      w[j + 1] = fma(-ci, row[j + 1], w[j + 1]);
+      Rw[j + 1][i] = w[j + 1];
+      wave_lds_sync();
+    }
+    // element (j + 2, j + 2) after this step, for the next pivot
+    if (j + 2 < OBW) {
+      w[j + 2] = fma(-ci, row[j + 2], w[j + 2]);
+      a = readlane_f64(w[j + 2], j + 2);
+      row[j + 2] = Rw[j + 1][j + 2];
+    }
+    const int k0 = j + 3, nk = OBW - k0 > 0 ? OBW - k0 : 0;
+    const int q1 = k0 + nk / 4, q2 = k0 + nk / 2, q3 = k0 + (3 * nk) / 4;
+    double e = 0.0;
+#pragma unroll
+    for (int k = k0; k < q1; ++k) w[k] = fma(-ci, row[k], w[k]);
+#pragma unroll
+    for (int k = k0; k < q1; ++k) row[k] = Rw[j + 1][k];
+    __builtin_amdgcn_sched_barrier(0);
+    e = fma(-dn, y, 1.0);
+#pragma unroll
+    for (int k = q1; k < q2; ++k) w[k] = fma(-ci, row[k], w[k]);
+#pragma unroll
+    for (int k = q1; k < q2; ++k) row[k] = Rw[j + 1][k];
+    __builtin_amdgcn_sched_barrier(0);
+    e = fma(e, e, e);
+#pragma unroll
+    for (int k = q2; k < q3; ++k) w[k] = fma(-ci, row[k], w[k]);
+#pragma unroll
+    for (int k = q2; k < q3; ++k) row[k] = Rw[j + 1][k];
+    __builtin_amdgcn_sched_barrier(0);
+    y = fma(y, e, y);
+#pragma unroll
+    for (int k = q3; k < OBW; ++k) w[k] = fma(-ci, row[k], w[k]);
+#pragma unroll
+    for (int k = q3; k < OBW; ++k) row[k] = Rw[j + 1][k];
+    __builtin_amdgcn_sched_barrier(0);
+    d = dn;
+    rc = y;
+    live = liven;
+  }
+  const bool live_i = my_d > 0.0 && gii != 0.0;
+  const double rinv_i = live_i ? rsq_nr(my_d) : 0.0;
+
   // acceptance: every nonzero column keeps a pivot d_j >= delta G_jj and, on
   // the first visit, no column is at or below 1e-13 of its original norm;
-  // exactly zero columns are dead (wave 0 holds the columns)
-  bool ok = true;
-  if (t < 64) {
-    const double delta = final ? 0.25 : 1e-12;
-    bool good_j = true;
-    if (t < nb) {
-      const bool dd = gd[t] == 0.0;
-      isdead[t] = dd ? 1 : 0;
-      if (!dd) good_j = (pd[t] >= delta * gd[t]) && (final || sgd[t] > dead_tol * n0[t]);
-    }
-    ok = __all(good_j);
-  }
-  // R in full: R[r][k] = Rw[r][k] rinv[r] (k > r), R[r][r] = sqrt(d_r), zero
-  // below; then R^{-1} by blocks of 16: the four diagonal blocks inverted at
-  // once (a column per thread, back substitution), then the blocks above the
-  // diagonal by block back substitution, X_ij = -X_ii sum_{i<k<=j} R_ik X_kj,
-  // one diagonal distance j - i at a time
-  for (int e = t; e < OBW * OBW; e += 256) {
-    const int r = e >> 6, k = e & 63;
-    const double ir = rinv[r];
-    Rw[r][k] = k > r ? Rw[r][k] * ir : (k == r && ir > 0.0 ? 1.0 / ir : 0.0);
-    X[r][k] = 0.0;
-  }
-  __syncthreads();
-  if (t < OBW) {
-    const int b0 = t & ~15, c = t & 15;   // block origin, column in the block
-    for (int r = c; r >= 0; --r) {
-      double s4[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int k = r + 1; k <= c; ++k) s4[k & 3] += Rw[b0 + r][b0 + k] * X[b0 + k][b0 + c];
-      const double ir = rinv[b0 + r];
-      X[b0 + r][b0 + c] = ((r == c ? 1.0 : 0.0) - ((s4[0] + s4[1]) + (s4[2] + s4[3]))) * ir;
-    }
-  }
-  __syncthreads();
-  __shared__ double Tb[3][16][17];
-  for (int dist = 1; dist < 4; ++dist) {
-    const int nblk = 4 - dist;   // blocks (i, i + dist), i < nblk
-    // T_i = sum_{k = i+1}^{i+dist} R_{i k} X_{k, i+dist}
-    for (int e = t; e < nblk * 256; e += 256) {
-      const int bi = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
-      const int bj = bi + dist;
-      double s4[4] = {0.0, 0.0, 0.0, 0.0};
-      for (int bk = bi + 1; bk <= bj; ++bk)
+  // exactly zero columns are dead
+  const double delta = final ? 0.25 : 1e-12;
+  const bool isdead = i < nb && gii == 0.0;
+  bool good_i = true;
+  if (i < nb && !isdead)
+    good_i = (my_d >= delta * gii) && (final || sqrt(gii) > dead_tol * n0);
+  const bool ok = __all(good_i);
+
+  // row i of R^{-1}: acc_m collects sum_{k<m} L[m][k] y_k with
+  // L[m][k] = Rw[k][m] / sqrt(d_k), i.e. Rw[k][m] z_k, z_k = y_k / sqrt(d_k)
+  double acc[OBW];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) s4[q & 3] += Rw[16 * bi + rr][16 * bk + q] * X[16 * bk + q][16 * bj + cc];
-      Tb[bi][rr][cc] = (s4[0] + s4[1]) + (s4[2] + s4[3]);
-    }
-    __syncthreads();
-    // X_{i, i+dist} = -X_ii T_i
-    for (int e = t; e < nblk * 256; e += 256) {
-      const int bi = e >> 8, rr = (e >> 4) & 15, cc = e & 15;
-      const int bj = bi + dist;
-      double s4[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < OBW; ++k) acc[k] = 0.0;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) s4[q & 3] += X[16 * bi + rr][16 * bi + q] * Tb[bi][q][cc];
-      X[16 * bi + rr][16 * bj + cc] = -((s4[0] + s4[1]) + (s4[2] + s4[3]));
+  for (int k = 1; k < OBW; ++k) row[k] = Rw[0][k];
+  double part = 0.0;
+  double rk = readlane_f64(rinv_i, 0);
+  double z = (i == 0 ? 1.0 : 0.0) * (rk * rk);
+#pragma clang loop unroll(full)
+  for (int k = 0; k < OBW; ++k) {
+    const double y = fma(-acc[k], rk, (i == k ? 1.0 : 0.0) * rk);
+    double zn = 0.0, rn = 0.0;
+    if (k + 1 < OBW) {
+      acc[k + 1] = fma(row[k + 1], z, acc[k + 1]);
+      rn = readlane_f64(rinv_i, k + 1);
+      zn = fma(-acc[k + 1], rn * rn, (i == k + 1 ? 1.0 : 0.0) * (rn * rn));
     }
-    __syncthreads();
+    const int m0 = k + 2, nm = OBW - m0 > 0 ? OBW - m0 : 0;
+    const int h = m0 + nm / 2;
+#pragma unroll
+    for (int m = m0; m < h; ++m) acc[m] = fma(row[m], z, acc[m]);
+#pragma unroll
+    for (int m = m0; m < h; ++m) row[m] = Rw[k + 1][m];
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = h; m < OBW; ++m) acc[m] = fma(row[m], z, acc[m]);
+#pragma unroll
+    for (int m = h; m < OBW; ++m) row[m] = Rw[k + 1][m];
+    acc[k] = y;   // row i of R^{-1}, element k
+    part = fma(y, y, part);
+    __builtin_amdgcn_sched_barrier(0);
+    z = zn;
+    rk = rn;
   }
-  if (t == 0) ok_s = ok ? 1 : 0;
-  __syncthreads();
-  if (t < 64) {
-    double part = 0.0;
-    int live = 0;
-    if (t < nb) {
-      for (int r = 0; r <= t; ++r) {
-        const double x = sgd[r] * X[r][t];
-        part += x * x;
-      }
-      live = isdead[t] ? 0 : 1;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      part += __shfl_xor(part, off);
-      live += __shfl_xor(live, off);
-    }
-    const double kappa = sqrt((double)live * part);
-    const int good = shift > 0.0 ||
-                     (ok_s && (kappa <= (final ? 2.0 * (double)(live > 0 ? live : 1) : 1e6)));
-    if (t < nb) {
-      for (int r = 0; r < nb; ++r) Ri[r * nb + t] = X[r][t];
-      if (!final && good) dead[c0 + t] = isdead[t];
-    }
-    if (t == 0) *healthy = good;
+  // kappa of the column-scaled block: || diag(sqrt(G_jj)) R^{-1} ||_F times
+  // the square root of the number of live columns
+  part *= gii;
+  int nlive = (i < nb && !isdead) ? 1 : 0;
+  for (int off = 32; off > 0; off >>= 1) {
+    part += __shfl_xor(part, off);
+    nlive += __shfl_xor(nlive, off);
   }
+  const double kappa = sqrt((double)nlive * part);
+  const int good = shift > 0.0 ||
+                   (ok && (kappa <= (final ? 2.0 * (double)(nlive > 0 ? nlive : 1) : 1e6)));
+  if (i < nb) {
+#pragma unroll
+    for (int k = 0; k < OBW; ++k)
+      if (k < nb) Ri[i * nb + k] = acc[k];
+    if (!final && good) dead[c0 + i] = isdead ? 1 : 0;
+  }
+  if (i == 0) *healthy = good;
 }
 
 // U[:, c0 : c0 + nb] <- U[:, c0 : c0 + nb] Ri (row-major, ld kk), when the
-// block is healthy.  Each workgroup takes 64 rows.
+// block is healthy.  Each workgroup takes 64 rows: the rows (transposed) and
+// Ri are staged in LDS, and each thread forms a 4 x 4 tile of the product,
+// wave w the columns 16 w .. 16 w + 15, so a step over the inner index reads
+// four 16-byte LDS words for sixteen FMAs.  R^{-1} is upper triangular, so a
+// wave stops at its last column; the products are summed in increasing
+// inner index, one accumulator per element.
 __global__ __launch_bounds__(256) void apply_ri_kernel(double* __restrict__ U, int m, int kk,
                                                        int c0, int nb,
                                                        const double* __restrict__ Ri,
                                                        const int* __restrict__ healthy) {
-  __shared__ double Rs[OBW][OBP];
-  __shared__ double P[64][OBP];
+  constexpr int LD = OBW + 4;         // 16-byte aligned rows
+  __shared__ double Rs[OBW][LD];      // Rs[a][c] = R^{-1}[a][c]
+  __shared__ double Pt[OBW][LD];      // Pt[a][r] = U[i0 + r][c0 + a]
   if (!*healthy) return;
   const int t = threadIdx.x;
   const int i0 = blockIdx.x * 64;
-  for (int e = t; e < nb * nb; e += 256) Rs[e / nb][e % nb] = Ri[e];
-  for (int e = t; e < 64 * nb; e += 256) {
-    const int r = e / nb, cc = e % nb;
-    P[r][cc] = (i0 + r < m) ? U[(int64_t)(i0 + r) * kk + c0 + cc] : 0.0;
-  }
-  __syncthreads();
-  // thread: column cc = t % 64 of rows t / 64 + 4 q (16 independent sums;
-  // R^{-1} is upper triangular, so only a <= cc contributes)
-  const int cc = t & 63, r0 = t >> 6;
-  if (cc >= nb) return;
-  double acc[16];
+  double rv[16], pv[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-  for (int a = 0; a <= cc; ++a) {
-    const double rv = Rs[a][cc];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] += P[r0 + 4 * q][a] * rv;
+  for (int q = 0; q < 16; ++q) {
+    const int r = (t >> 6) + 4 * q, cc = t & 63;
+    rv[q] = (r < nb && cc < nb) ? Ri[r * nb + cc] : 0.0;
+    pv[q] = (i0 + r < m && cc < nb) ? U[(int64_t)(i0 + r) * kk + c0 + cc] : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    const int r = r0 + 4 * q;
-    if (i0 + r < m) U[(int64_t)(i0 + r) * kk + c0 + cc] = acc[q];
+    const int r = (t >> 6) + 4 * q, cc = t & 63;
+    Rs[r][cc] = rv[q];
+    Pt[cc][r] = pv[q];
+  }
+  __syncthreads();
+  const int w = t >> 6, lane = t & 63;
+  const int rb = (lane >> 2) * 4, cb = w * 16 + (lane & 3) * 4;
+  const int amax = min(nb, w * 16 + 16);   // R^{-1}[a][c] = 0 for a > c
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+  for (int a = 0; a < amax; ++a) {
+    const double2 p01 = *reinterpret_cast<const double2*>(&Pt[a][rb]);
+    const double2 p23 = *reinterpret_cast<const double2*>(&Pt[a][rb + 2]);
+    const double2 r01 = *reinterpret_cast<const double2*>(&Rs[a][cb]);
+    const double2 r23 = *reinterpret_cast<const double2*>(&Rs[a][cb + 2]);
+    const double p[4] = {p01.x, p01.y, p23.x, p23.y};
+    const double rr[4] = {r01.x, r01.y, r23.x, r23.y};
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = fma(p[i], rr[j], acc[i][j]);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int row = i0 + rb + i;
+    if (row >= m) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (cb + j < nb) U[(int64_t)row * kk + c0 + cb + j] = acc[i][j];
   }
 }
 
@@ -1006,13 +1066,13 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
         {
           // Cholesky nb^3 / 3 and triangular inverse nb^3 / 3 flop; G in, R^{-1} out
           const double b3 = (double)nbk * nbk * nbk;
-          ProfScope ps(c, K_CHOL, 2.0 * b3 / 3.0, 8.0 * 2.0 * nbk * nbk);
-          hipLaunchKernelGGL(chol_block_kernel, dim3(1), dim3(256), 0, c.stream, Gb, nbk, c0, nrm0,
+          ProfScope ps(c, K_CHOL, 2.0 * b3 / 3.0, 8.0 * 2.0 * nbk * nbk, 1, true);
+          launch(ps, chol_block_kernel, dim3(1), dim3(64), c.stream, Gb, nbk, c0, nrm0,
                              dead, loose ? 0 : pass, Ri, healthy, shifted ? 1e-12 : 0.0,
                              dead_tol());
         }
-        ProfScope ps(c, K_SVD_OTHER, 2.0 * m * nbk * nbk, 8.0 * 2.0 * m * nbk);
-        hipLaunchKernelGGL(apply_ri_kernel, dim3((m + 63) / 64), dim3(256), 0, c.stream, A, m, kk,
+        ProfScope ps(c, K_SVD_OTHER, 2.0 * m * nbk * nbk, 8.0 * 2.0 * m * nbk, 1, true);
+        launch(ps, apply_ri_kernel, dim3((m + 63) / 64), dim3(256), c.stream, A, m, kk,
                            c0, nbk, Ri, healthy);
         c.check_launch();
       }
@@ -1125,15 +1185,13 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
     // megabytes apart, so they mostly land on different XCDs)
     const int xslot = (int)(((uintptr_t)X >> 20) & 7);
     for (int sw = 0; sw < max_sweeps; ++sw) {
-      {
-        // the rounds of a sweep are timed as one span (events around every
-        // launch would add each launch's dispatch to its duration); the
-        // work is data dependent: the kernel tallies it on the device
-        ProfScope ps(c, K_SVD_ROUND, 0.0, 0.0, nb - 1);
-        for (int rd = 0; rd < nb - 1; ++rd)
-          hipLaunchKernelGGL(jac_round_kernel, dim3(8 * (nb / 2)), dim3(256), 0, c.stream, X, r,
-                             (int64_t)r, V, n, nb, rd, tol, tol_in, inner_sweeps, fro, flags,
-                             c.prof ? c.work : nullptr, xslot, thr_mult);
+      for (int rd = 0; rd < nb - 1; ++rd) {
+        // each round timed by its own dispatch; its work is data dependent,
+        // so the kernel tallies it on the device
+        ProfScope ps(c, K_SVD_ROUND, 0.0, 0.0, 1, true);
+        launch(ps, jac_round_kernel, dim3(8 * (nb / 2)), dim3(256), c.stream, X, r, (int64_t)r, V,
+               n, nb, rd, tol, tol_in, inner_sweeps, fro, flags, c.prof ? c.work : nullptr, xslot,
+               thr_mult);
       }
       hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(1), 0, c.stream, flags);
     }
