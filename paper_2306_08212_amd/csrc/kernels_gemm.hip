@@ -161,36 +161,104 @@ __global__ __launch_bounds__(256) void gemm_f32_kernel(
     for (int j = 0; j < 2; ++j)
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.0f;
 
-  float ra[8], rb[8];
+  // tiles are fetched as 16-byte vectors along the operand's contiguous
+  // dimension (two per operand and thread) when the leading dimension and
+  // the base keep them aligned; ragged edges fall back to guarded scalars
+  const bool va = (lda % 4 == 0) && (((uintptr_t)A & 15) == 0);
+  const bool vb = (ldb % 4 == 0) && (((uintptr_t)B & 15) == 0);
+  float4 ra[2], rb[2];
   auto load_tiles = [&](int k0) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + q * 256;
-      int mm, kk;
-      if (!ta) { mm = e / F32_BK; kk = e % F32_BK; } else { kk = e / F32_BM; mm = e % F32_BM; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      float v = 0.0f;
-      if (gm < M && gk < K) v = ta ? A[(int64_t)gk * lda + gm] : A[(int64_t)gm * lda + gk];
-      ra[q] = v;
-      int nn;
-      if (!tb) { kk = e / F32_BN; nn = e % F32_BN; } else { nn = e / F32_BK; kk = e % F32_BK; }
-      const int gn = n0 + nn;
-      const int gk2 = k0 + kk;
-      float w = 0.0f;
-      if (gn < N && gk2 < K) w = tb ? B[(int64_t)gn * ldb + gk2] : B[(int64_t)gk2 * ldb + gn];
-      rb[q] = w;
+    for (int h = 0; h < 2; ++h) {
+      const int q4 = tid + 256 * h;
+      // A: ta = 0 is m x k (quads along k), ta = 1 is k x m (quads along m)
+      {
+        const int mm = ta ? (q4 % (F32_BM / 4)) * 4 : q4 / (F32_BK / 4);
+        const int kk = ta ? q4 / (F32_BM / 4) : (q4 % (F32_BK / 4)) * 4;
+        const int gm = m0 + mm, gk = k0 + kk;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (!ta) {
+          if (va && gm < M && gk + 3 < K) {
+            v = *reinterpret_cast<const float4*>(A + (int64_t)gm * lda + gk);
+          } else if (gm < M) {
+            const float* p = A + (int64_t)gm * lda;
+            v.x = gk < K ? p[gk] : 0.0f;
+            v.y = gk + 1 < K ? p[gk + 1] : 0.0f;
+            v.z = gk + 2 < K ? p[gk + 2] : 0.0f;
+            v.w = gk + 3 < K ? p[gk + 3] : 0.0f;
+          }
+        } else {
+          if (va && gk < K && gm + 3 < M) {
+            v = *reinterpret_cast<const float4*>(A + (int64_t)gk * lda + gm);
+          } else if (gk < K) {
+            const float* p = A + (int64_t)gk * lda;
+            v.x = gm < M ? p[gm] : 0.0f;
+            v.y = gm + 1 < M ? p[gm + 1] : 0.0f;
+            v.z = gm + 2 < M ? p[gm + 2] : 0.0f;
+            v.w = gm + 3 < M ? p[gm + 3] : 0.0f;
+          }
+        }
+        ra[h] = v;
+      }
+      // B: tb = 0 is k x n (quads along n), tb = 1 is n x k (quads along k)
+      {
+        const int nn = tb ? q4 / (F32_BK / 4) : (q4 % (F32_BN / 4)) * 4;
+        const int kk = tb ? (q4 % (F32_BK / 4)) * 4 : q4 / (F32_BN / 4);
+        const int gn = n0 + nn, gk = k0 + kk;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (!tb) {
+          if (vb && gk < K && gn + 3 < N) {
+            v = *reinterpret_cast<const float4*>(B + (int64_t)gk * ldb + gn);
+          } else if (gk < K) {
+            const float* p = B + (int64_t)gk * ldb;
+            v.x = gn < N ? p[gn] : 0.0f;
+            v.y = gn + 1 < N ? p[gn + 1] : 0.0f;
+            v.z = gn + 2 < N ? p[gn + 2] : 0.0f;
+            v.w = gn + 3 < N ? p[gn + 3] : 0.0f;
+          }
+        } else {
+          if (vb && gn < N && gk + 3 < K) {
+            v = *reinterpret_cast<const float4*>(B + (int64_t)gn * ldb + gk);
+          } else if (gn < N) {
+            const float* p = B + (int64_t)gn * ldb;
+            v.x = gk < K ? p[gk] : 0.0f;
+            v.y = gk + 1 < K ? p[gk + 1] : 0.0f;
+            v.z = gk + 2 < K ? p[gk + 2] : 0.0f;
+            v.w = gk + 3 < K ? p[gk + 3] : 0.0f;
+          }
+        }
+        rb[h] = v;
+      }
     }
   };
   auto store_tiles = [&]() {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + q * 256;
-      int mm, kk;
-      if (!ta) { mm = e / F32_BK; kk = e % F32_BK; } else { kk = e / F32_BM; mm = e % F32_BM; }
-      As[kk][mm] = ra[q];
-      int nn;
-      if (!tb) { kk = e / F32_BN; nn = e % F32_BN; } else { nn = e / F32_BK; kk = e % F32_BK; }
-      Bs[kk][nn] = rb[q];
+    for (int h = 0; h < 2; ++h) {
+      const int q4 = tid + 256 * h;
+      {
+        const int mm = ta ? (q4 % (F32_BM / 4)) * 4 : q4 / (F32_BK / 4);
+        const int kk = ta ? q4 / (F32_BM / 4) : (q4 % (F32_BK / 4)) * 4;
+        if (!ta) {
+          As[kk][mm] = ra[h].x;
+          As[kk + 1][mm] = ra[h].y;
+          As[kk + 2][mm] = ra[h].z;
+          As[kk + 3][mm] = ra[h].w;
+        } else {
+          *reinterpret_cast<float4*>(&As[kk][mm]) = ra[h];
+        }
+      }
+      {
+        const int nn = tb ? q4 / (F32_BK / 4) : (q4 % (F32_BN / 4)) * 4;
+        const int kk = tb ? (q4 % (F32_BK / 4)) * 4 : q4 / (F32_BN / 4);
+        if (!tb) {
+          *reinterpret_cast<float4*>(&Bs[kk][nn]) = rb[h];
+        } else {
+          Bs[kk][nn] = rb[h].x;
+          Bs[kk + 1][nn] = rb[h].y;
+          Bs[kk + 2][nn] = rb[h].z;
+          Bs[kk + 3][nn] = rb[h].w;
+        }
+      }
     }
   };
   load_tiles(0);

@@ -31,7 +31,7 @@ def test_gemm_fp64(m, n, k, ta, tb):
 
 
 @pytest.mark.parametrize("m,n,k", GEMM_SHAPES)
-@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1)])
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 1), (0, 1), (1, 0)])
 def test_gemm_fp32_and_bf16(m, n, k, ta, tb):
     log("gemm f32/bf16", m, n, k, ta, tb)
     t = torch()
