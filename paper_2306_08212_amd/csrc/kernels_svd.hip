@@ -401,7 +401,8 @@ __global__ __launch_bounds__(256) void gather_cols_kernel(const double* __restri
        e += (int64_t)gridDim.x * 256) {
     const int64_t i = e / n;
     const int t = (int)(e % n);
-    Q[e] = M[i * n + order[t]];
+    const int j = order[t];
+    Q[e] = (j >= 0 && j < n) ? M[i * n + j] : 0.0;   // j is always in range (see the ranking)
   }
 }
 
@@ -425,14 +426,18 @@ __global__ __launch_bounds__(256) void jac_colnorm_kernel(const double* __restri
 }
 
 // order[rank] = column, for ranks < kk (descending norm, ties by index)
+// A NaN ranks below every number (as -inf, ties by index), so the ranks are
+// always a permutation of 0..c-1 and order[] holds valid column indices
+// whatever the data: the indices feed gathers.
 __global__ __launch_bounds__(256) void jac_rank_kernel(const double* __restrict__ sig, int c, int kk,
                                                        int* __restrict__ order) {
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= c) return;
-  const double v = sig[j];
+  auto key = [](double x) { return x == x ? x : -INFINITY; };
+  const double v = key(sig[j]);
   int rank = 0;
   for (int i = 0; i < c; ++i) {
-    const double w = sig[i];
+    const double w = key(sig[i]);
     rank += (w > v) || (w == v && i < j);
   }
   if (rank < kk) order[rank] = j;
@@ -442,18 +447,22 @@ __global__ __launch_bounds__(256) void jac_rank_kernel(const double* __restrict_
 // rotations V (col-major, vr rows), S[t] its singular value; columns with
 // sigma <= tau * sigma_0 (or not finite) are zero with S = 0.
 __global__ __launch_bounds__(256) void jac_pick_kernel(const double* __restrict__ V, int vr,
-                                                       const double* __restrict__ sig,
+                                                       int cp, const double* __restrict__ sig,
                                                        const int* __restrict__ order, int kk,
                                                        double tau, double* __restrict__ Uj,
                                                        double* __restrict__ S) {
   const int64_t total = (int64_t)vr * kk;
-  const double s0 = sig[order[0]];
+  // order[] is a permutation of 0..cp-1 (see the ranking); the range checks
+  // only keep a bad index from becoming an address
+  const int o0 = order[0];
+  const double s0 = (o0 >= 0 && o0 < cp) ? sig[o0] : 0.0;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * 256) {
     const int i = (int)(e / kk), t = (int)(e % kk);
     const int j = order[t];
-    const double sj = sig[j];
-    const bool keep = (s0 > 0.0) && (sj > tau * s0) && isfinite(sj);
+    const bool inr = j >= 0 && j < cp;
+    const double sj = inr ? sig[j] : 0.0;
+    const bool keep = inr && (s0 > 0.0) && (sj > tau * s0) && isfinite(sj);
     Uj[e] = keep ? V[(int64_t)j * vr + i] : 0.0;
     if (i == 0) S[t] = keep ? sj : 0.0;
   }
@@ -1209,7 +1218,7 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
     hipLaunchKernelGGL(jac_rank_kernel, dim3((cp + 255) / 256), dim3(256), 0, c.stream, sig, cp,
                        kk, order);
     hipLaunchKernelGGL(jac_pick_kernel, dim3(grid_for((int64_t)n * kk, 4096)), dim3(256), 0,
-                       c.stream, V, n, sig, order, kk, tau, Uj, S);
+                       c.stream, V, n, cp, sig, order, kk, tau, Uj, S);
     c.check_launch();
   }
   gemm(c, F64, n, kk, n, 1.0, Q3, n, 0, Uj, kk, 0, 0.0, A1, kk);        // Q3 J
