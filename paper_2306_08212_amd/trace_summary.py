@@ -64,7 +64,8 @@ def main(argv=None):
     ap.add_argument("dir")
     ap.add_argument("--steps", type=int, required=True, help="timed moves of the bench run")
     ap.add_argument("--profiled", type=int, default=4, help="moves of the profiled pass")
-    ap.add_argument("--kernel", default="gemm_f64_kernel")
+    ap.add_argument("--kernel", default="gemm_f64_kernel",
+                    help="kernel (or kernels joined by +) whose average is reported")
     a = ap.parse_args(argv)
     ev = load(a.dir)
     hdr = "| kernel | launches | total ms | avg us | % |\n|---|---:|---:|---:|---:|"
@@ -105,8 +106,10 @@ def main(argv=None):
     print(f"\n### Profiled pass ({a.profiled} moves, gate kernels excluded)\n")
     print("| kernel | launches per move | ms per move | avg us | % |\n|---|---:|---:|---:|---:|")
     print("\n".join(rows))
-    if a.kernel in tot:
-        c, ms = tot[a.kernel]
+    names = [k for k in a.kernel.split("+") if k in tot]
+    if names:
+        c = sum(tot[k][0] for k in names)
+        ms = sum(tot[k][1] for k in names)
         print(f"\n`{a.kernel}` in the profiled pass: {c} launches, average {1e3 * ms / c:.2f} us.")
     return 0
 
