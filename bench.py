@@ -31,7 +31,7 @@ PEAK = {"gemm_f64": (78.6e12, "TFLOP/s", "mfma"), "gemm_f32": (157.3e12, "TFLOP/
         "svd_round": (78.6e12, "TFLOP/s", "alu"), "chol": (78.6e12, "TFLOP/s", "alu")}
 KERNEL_OF = {"gemm_f64": "gemm_f64_kernel", "gemm_f32": "gemm_f32_kernel",
              "gemm_bf16": "gemm_bf16_kernel", "permute": "permute_ctile_kernel/permute_rows_kernel",
-             "svd_round": "jac_round_kernel", "chol": "chol_block_kernel"}
+             "svd_round": "jac_round_kernel", "chol": "chol_apply_kernel"}
 # HBM bytes per launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE, for a
 # kernel whose code is the one the counters were taken on; none is listed
 # for the current kernels (the roofline's traffic is then null).

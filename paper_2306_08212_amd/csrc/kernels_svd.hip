@@ -648,8 +648,8 @@ __global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restric
 }
 
 // Cholesky path of the in-block step.  G (nb x nb) is the Gram matrix of the
-// block's columns after the projection of the earlier blocks.  One
-// workgroup factors G = R^T R and inverts R.  The block is "healthy" when the
+// block's columns after the projection of the earlier blocks.  One wave
+// factors G = R^T R and inverts R.  The block is "healthy" when the
 // condition number of the column-scaled block, estimated from R^{-1}, is at
 // most 1e6 on the first visit (Cholesky QR then leaves orthogonality errors
 // below ~1e-4, which the second visit removes) and at most twice its value
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restric
 // 0.25: unit columns that lose more than half their length are left to the
 // Gram-Schmidt fallback, which decides dependence), and on the first visit
 // no column is at or below 1e-13 of its original norm.  Exactly zero columns
-// are dead.  Ri = R^{-1} (dead rows and columns zero).
+// are dead.  R^{-1} has its dead rows and columns zero.
 //
 // With shift > 0 the factorisation is of G + shift diag(G) and the block is
 // taken as it comes (no condition test): Q = A R^{-1} then spans exactly the
@@ -691,12 +691,19 @@ __device__ __forceinline__ double rcp_cubic(double x, double y0) {
   return fma(y0, fma(e, e, e), y0);
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_block_kernel(
-    const double* __restrict__ G, int nb, int c0, const double* __restrict__ nrm0,
-    int* __restrict__ dead, int final, double* __restrict__ Ri, int* __restrict__ healthy,
-    double shift, double dead_tol) {
-  __shared__ double Rw[OBW][OBP];   // row j of the trailing matrix as it stood at step j
-  __shared__ double Gs[OBW][OBP];   // G, staged with coalesced loads
+constexpr int RLD = OBW + 4;   // 16-byte aligned LDS rows of R^{-1} and of the applied rows
+
+// Run by the first wave of a workgroup (lanes 0..63): factors G, writes R^{-1}
+// into Rs (row-major, zero beyond nb) and returns whether the block is
+// healthy; with write_state it also records healthy and the dead columns.
+// Rw and Gs are LDS scratch.
+__device__ __forceinline__ int chol_factor(const double* __restrict__ G, int nb, int c0,
+                                           const double* __restrict__ nrm0,
+                                           int* __restrict__ dead, int final,
+                                           int* __restrict__ healthy, double shift,
+                                           double dead_tol, bool write_state,
+                                           double (*Rw)[OBP], double (*Gs)[OBP],
+                                           double (*Rs)[RLD]) {
   const int i = threadIdx.x;
   {
     // clamped addresses: every load is issued, out-of-range values dropped
@@ -839,43 +846,54 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void
   const double kappa = sqrt((double)nlive * part);
   const int good = shift > 0.0 ||
                    (ok && (kappa <= (final ? 2.0 * (double)(nlive > 0 ? nlive : 1) : 1e6)));
-  if (i < nb) {
 #pragma unroll
-    for (int k = 0; k < OBW; ++k)
-      if (k < nb) Ri[i * nb + k] = acc[k];
-    if (!final && good) dead[c0 + i] = isdead ? 1 : 0;
+  for (int k = 0; k < OBW; ++k) Rs[i][k] = acc[k];   // zero beyond nb
+  if (write_state) {
+    if (i < nb && !final && good) dead[c0 + i] = isdead ? 1 : 0;
+    if (i == 0) *healthy = good;
   }
-  if (i == 0) *healthy = good;
+  return good;
 }
 
-// U[:, c0 : c0 + nb] <- U[:, c0 : c0 + nb] Ri (row-major, ld kk), when the
-// block is healthy.  Each workgroup takes 64 rows: the rows (transposed) and
-// Ri are staged in LDS, and each thread forms a 4 x 4 tile of the product,
-// wave w the columns 16 w .. 16 w + 15, so a step over the inner index reads
-// four 16-byte LDS words for sixteen FMAs.  R^{-1} is upper triangular, so a
-// wave stops at its last column; the products are summed in increasing
-// inner index, one accumulator per element.
-__global__ __launch_bounds__(256) void apply_ri_kernel(double* __restrict__ U, int m, int kk,
-                                                       int c0, int nb,
-                                                       const double* __restrict__ Ri,
-                                                       const int* __restrict__ healthy) {
-  constexpr int LD = OBW + 4;         // 16-byte aligned rows
-  __shared__ double Rs[OBW][LD];      // Rs[a][c] = R^{-1}[a][c]
-  __shared__ double Pt[OBW][LD];      // Pt[a][r] = U[i0 + r][c0 + a]
-  if (!*healthy) return;
+// The in-block Cholesky QR step: the factorisation of G (chol_factor) and
+// U[:, c0 : c0 + nb] <- U[:, c0 : c0 + nb] R^{-1} (row-major, ld kk) when the
+// block is healthy, in one launch.  Each workgroup takes 64 rows of U; its
+// first wave factors G (every workgroup the same arithmetic on the same G,
+// so the same R^{-1} and verdict; the first workgroup records them), which
+// costs no time over one factorisation and saves a launch and a round trip
+// of R^{-1} through memory.  Apply: the rows (transposed) sit in LDS next to
+// R^{-1}, and each thread forms a 4 x 4 tile of the product, wave w the
+// columns 16 w .. 16 w + 15, so a step over the inner index reads four
+// 16-byte LDS words for sixteen FMAs.  R^{-1} is upper triangular, so a wave
+// stops at its last column; the products are summed in increasing inner
+// index, one accumulator per element.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_apply_kernel(
+    const double* __restrict__ G, int nb, int c0, const double* __restrict__ nrm0,
+    int* __restrict__ dead, int final, int* __restrict__ healthy, double shift, double dead_tol,
+    double* __restrict__ U, int m, int kk) {
+  __shared__ double Rw[OBW][OBP];   // row j of the trailing matrix as it stood at step j
+  __shared__ double Gs[OBW][OBP];   // G, staged with coalesced loads
+  __shared__ double Rs[OBW][RLD];   // Rs[a][c] = R^{-1}[a][c]
+  __shared__ double Pt[OBW][RLD];   // Pt[a][r] = U[i0 + r][c0 + a]
+  __shared__ int good_s;
   const int t = threadIdx.x;
+  if (t < 64) {
+    const int good = chol_factor(G, nb, c0, nrm0, dead, final, healthy, shift, dead_tol,
+                                 blockIdx.x == 0, Rw, Gs, Rs);
+    if (t == 0) good_s = good;
+  }
+  __syncthreads();
+  if (!good_s) return;
   const int i0 = blockIdx.x * 64;
-  double rv[16], pv[16];
+  double pv[16];
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int r = (t >> 6) + 4 * q, cc = t & 63;
-    rv[q] = (r < nb && cc < nb) ? Ri[r * nb + cc] : 0.0;
     pv[q] = (i0 + r < m && cc < nb) ? U[(int64_t)(i0 + r) * kk + c0 + cc] : 0.0;
   }
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int r = (t >> 6) + 4 * q, cc = t & 63;
-    Rs[r][cc] = rv[q];
     Pt[cc][r] = pv[q];
   }
   __syncthreads();
@@ -1050,7 +1068,6 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
   int* dead = (int*)c.arena.alloc(sizeof(int) * (size_t)kk);
   double* G = (double*)c.arena.alloc(sizeof(double) * (size_t)kk * OB);
   double* Gb = (double*)c.arena.alloc(sizeof(double) * OB * OB);
-  double* Ri = (double*)c.arena.alloc(sizeof(double) * OB * OB);
   int* healthy = (int*)c.arena.alloc(sizeof(int));
   if (!c.dry) {
     ProfScope ps(c, K_SVD_OTHER, 0.0, 8.0 * (double)m * kk);
@@ -1072,17 +1089,15 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
       gemm(c, F64, nbk, nbk, m, 1.0, A + c0, kk, 1, A + c0, kk, 0, 0.0, Gb, nbk);
       if (!c.dry) {
         const bool shifted = loose && pass == 0;
-        {
-          // Cholesky nb^3 / 3 and triangular inverse nb^3 / 3 flop; G in, R^{-1} out
-          const double b3 = (double)nbk * nbk * nbk;
-          ProfScope ps(c, K_CHOL, 2.0 * b3 / 3.0, 8.0 * 2.0 * nbk * nbk, 1, true);
-          launch(ps, chol_block_kernel, dim3(1), dim3(64), c.stream, Gb, nbk, c0, nrm0,
-                             dead, loose ? 0 : pass, Ri, healthy, shifted ? 1e-12 : 0.0,
-                             dead_tol());
-        }
-        ProfScope ps(c, K_SVD_OTHER, 2.0 * m * nbk * nbk, 8.0 * 2.0 * m * nbk, 1, true);
-        launch(ps, apply_ri_kernel, dim3((m + 63) / 64), dim3(256), c.stream, A, m, kk,
-                           c0, nbk, Ri, healthy);
+        // Cholesky nb^3 / 3 and triangular inverse nb^3 / 3 flop (once: the
+        // workgroups repeat it side by side), apply m nb^2; G in, the block
+        // read and written
+        const double b3 = (double)nbk * nbk * nbk;
+        ProfScope ps(c, K_CHOL, 2.0 * b3 / 3.0 + (double)m * nbk * nbk,
+                     8.0 * ((double)nbk * nbk + 2.0 * m * nbk), 1, true);
+        launch(ps, chol_apply_kernel, dim3((m + 63) / 64), dim3(256), c.stream, (const double*)Gb,
+               nbk, c0, (const double*)nrm0, dead, loose ? 0 : pass, healthy,
+               shifted ? 1e-12 : 0.0, dead_tol(), A, m, kk);
         c.check_launch();
       }
       if (!(loose && pass == 0)) tsqr_fallback(c, A, m, kk, c0, nbk, nrm0, dead, loose ? 0 : pass, healthy);
