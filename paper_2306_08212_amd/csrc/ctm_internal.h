@@ -163,6 +163,18 @@ void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A,
           void* C, int64_t ldc, int batch = 1, int64_t sA = 0, int64_t sB = 0,
           int64_t sC = 0);
 
+// Most K slabs an FP64 product is split into.
+constexpr int kMaxF64Splits = 32;
+
+// The FP64 product op(A) op(B) (m x n, row-major) over K split as gemm()
+// splits it, for a consumer that sums the slabs itself: slab z of part (at
+// z * m * n) holds the product over the z-th K range, and the sum of the
+// slabs in z order starting from 0.0 is gemm()'s result with alpha = 1,
+// beta = 0, bitwise.  With one slab part holds the product itself.  part has
+// room for kMaxF64Splits slabs.  Returns the number of slabs.
+int gemm_f64_partials(Ctx& c, int m, int n, int k, const double* A, int64_t lda, int ta,
+                      const double* B, int64_t ldb, int tb, double* part);
+
 // out = permute(in): out dims are in.dims[perm[i]]; dtype conversion allowed
 // (F64 <-> F32 <-> BF16) with an optional scale applied on the way.
 void permute(Ctx& c, const Tensor& in, const int* perm, Tensor& out,

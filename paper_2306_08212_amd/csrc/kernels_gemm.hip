@@ -363,7 +363,38 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(
       }
 }
 
+// K split of an FP64 product whose grid cannot fill the chip: the number of
+// slabs (1: none) and the K extent of each.
+int f64_splits(int m, int n, int k, int batch, int* kchunk) {
+  *kchunk = k;
+  const int64_t tiles = (int64_t)((m + F64_BM - 1) / F64_BM) * ((n + F64_BN - 1) / F64_BN) * batch;
+  if (tiles >= 256 || k < 256) return 1;
+  int64_t want = (512 + tiles - 1) / tiles;
+  want = std::min<int64_t>(want, std::min<int64_t>(kMaxF64Splits, k / 128));
+  if (want <= 1) return 1;
+  *kchunk = (int)(((k + want - 1) / want + F64_BK - 1) / F64_BK) * F64_BK;
+  return (k + *kchunk - 1) / *kchunk;
+}
+
 }  // namespace
+
+int gemm_f64_partials(Ctx& c, int m, int n, int k, const double* A, int64_t lda, int ta,
+                      const double* B, int64_t ldb, int tb, double* part) {
+  if (m <= 0 || n <= 0) return 0;
+  if (k < 0) k = 0;
+  int kchunk = k;
+  const int splits = f64_splits(m, n, k, 1, &kchunk);
+  if (c.dry) return splits;
+  const int tm = (m + F64_BM - 1) / F64_BM, tn = (n + F64_BN - 1) / F64_BN;
+  ProfScope ps(c, K_GEMM_F64, 2.0 * m * n * (double)k,
+               ((double)m * k + (double)k * n) * 8.0 + (double)m * n * 8.0 * splits, 1, true);
+  // one slab: the product itself (alpha = 1, beta = 0, which the kernel
+  // stores as alpha * acc, i.e. acc); several: the raw slabs
+  launch(ps, gemm_f64_kernel, dim3(tm * tn, 1, splits), dim3(256), c.stream, m, n, k, 1.0, A, lda,
+         ta, B, ldb, tb, 0.0, splits > 1 ? (double*)nullptr : part, (int64_t)n, (int64_t)0, (int64_t)0, (int64_t)0, tn, kchunk,
+         splits > 1 ? part : (double*)nullptr);
+  return splits;
+}
 
 void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A, int64_t lda,
           int ta, const void* B, int64_t ldb, int tb, double beta, void* C, int64_t ldc,
@@ -380,16 +411,8 @@ void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A, i
   double* part = nullptr;
   size_t mk = c.arena.mark();
   if (dtype == F64) {
-    const int64_t tiles = (int64_t)((m + F64_BM - 1) / F64_BM) * ((n + F64_BN - 1) / F64_BN) * batch;
     const bool have_arena = c.arena.dry || c.arena.base != nullptr;
-    if (have_arena && tiles < 256 && k >= 256) {
-      int64_t want = (512 + tiles - 1) / tiles;
-      want = std::min<int64_t>(want, std::min<int64_t>(32, k / 128));
-      if (want > 1) {
-        kchunk = (int)(((k + want - 1) / want + F64_BK - 1) / F64_BK) * F64_BK;
-        splits = (k + kchunk - 1) / kchunk;
-      }
-    }
+    if (have_arena) splits = f64_splits(m, n, k, batch, &kchunk);
     if (splits > 1) {
       part = (double*)c.arena.alloc(sizeof(double) * (size_t)splits * batch * m * n);
       if (part == nullptr && !c.dry) {   // no room: one pass over K

@@ -693,30 +693,19 @@ __device__ __forceinline__ double rcp_cubic(double x, double y0) {
 
 constexpr int RLD = OBW + 4;   // 16-byte aligned LDS rows of R^{-1} and of the applied rows
 
-// Run by the first wave of a workgroup (lanes 0..63): factors G, writes R^{-1}
-// into Rs (row-major, zero beyond nb) and returns whether the block is
-// healthy; with write_state it also records healthy and the dead columns.
-// Rw and Gs are LDS scratch.
-__device__ __forceinline__ int chol_factor(const double* __restrict__ G, int nb, int c0,
-                                           const double* __restrict__ nrm0,
+// Run by the first wave of a workgroup (lanes 0..63) once G sits in Gs (zero
+// beyond nb): factors G, writes R^{-1} into Rs (row-major, zero beyond nb)
+// and returns whether the block is healthy; with write_state it also
+// records healthy and the dead columns.  Rw is LDS scratch.
+__device__ __forceinline__ int chol_factor(int nb, int c0, const double* __restrict__ nrm0,
                                            int* __restrict__ dead, int final,
                                            int* __restrict__ healthy, double shift,
                                            double dead_tol, bool write_state,
-                                           double (*Rw)[OBP], double (*Gs)[OBP],
+                                           double (*Rw)[OBP], const double (*Gs)[OBP],
                                            double (*Rs)[RLD]) {
   const int i = threadIdx.x;
-  {
-    // clamped addresses: every load is issued, out-of-range values dropped
-    const int ic = i < nb ? i : nb - 1;
-    double g[OBW];
-#pragma unroll
-    for (int r = 0; r < OBW; ++r) g[r] = G[(r < nb ? r : nb - 1) * nb + ic];
-#pragma unroll
-    for (int r = 0; r < OBW; ++r) Gs[r][i] = (r < nb && i < nb) ? g[r] : 0.0;
-  }
-  const double gii = i < nb ? G[i * nb + i] : 0.0;
+  const double gii = Gs[i][i];
   const double n0 = i < nb ? nrm0[c0 + i] : 0.0;
-  wave_lds_sync();
 
   double w[OBW], row[OBW];
 #pragma unroll
@@ -857,7 +846,10 @@ __device__ __forceinline__ int chol_factor(const double* __restrict__ G, int nb,
 
 // The in-block Cholesky QR step: the factorisation of G (chol_factor) and
 // U[:, c0 : c0 + nb] <- U[:, c0 : c0 + nb] R^{-1} (row-major, ld kk) when the
-// block is healthy, in one launch.  Each workgroup takes 64 rows of U; its
+// block is healthy, in one launch.  G comes as the splits K slabs of its
+// product (gemm_f64_partials; one slab: G itself), which the workgroup sums
+// in slab order from 0.0 into LDS, the order of gemm()'s own sum, so G is
+// bitwise the one gemm() returns.  Each workgroup takes 64 rows of U; its
 // first wave factors G (every workgroup the same arithmetic on the same G,
 // so the same R^{-1} and verdict; the first workgroup records them), which
 // costs no time over one factorisation and saves a launch and a round trip
@@ -868,17 +860,49 @@ __device__ __forceinline__ int chol_factor(const double* __restrict__ G, int nb,
 // stops at its last column; the products are summed in increasing inner
 // index, one accumulator per element.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_apply_kernel(
-    const double* __restrict__ G, int nb, int c0, const double* __restrict__ nrm0,
+    const double* __restrict__ Gp, int splits, int nb, int c0, const double* __restrict__ nrm0,
     int* __restrict__ dead, int final, int* __restrict__ healthy, double shift, double dead_tol,
     double* __restrict__ U, int m, int kk) {
   __shared__ double Rw[OBW][OBP];   // row j of the trailing matrix as it stood at step j
-  __shared__ double Gs[OBW][OBP];   // G, staged with coalesced loads
+  __shared__ double Gs[OBW][OBP];   // G, zero beyond nb
   __shared__ double Rs[OBW][RLD];   // Rs[a][c] = R^{-1}[a][c]
   __shared__ double Pt[OBW][RLD];   // Pt[a][r] = U[i0 + r][c0 + a]
   __shared__ int good_s;
   const int t = threadIdx.x;
+  {
+    // element (r, cc) = (t / 64 + 4 q, t % 64); clamped addresses, so every
+    // load is issued and the values beyond nb are dropped
+    const int cc = t & 63, ccl = cc < nb ? cc : nb - 1;
+    const int64_t nn = (int64_t)nb * nb;
+    double g[16];
+    if (splits == 1) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int r = (t >> 6) + 4 * q;
+        g[q] = Gp[(r < nb ? r : nb - 1) * nb + ccl];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) g[q] = 0.0;
+#pragma unroll 2
+      for (int z = 0; z < splits; ++z) {
+        const double* slab = Gp + z * nn;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int r = (t >> 6) + 4 * q;
+          g[q] += slab[(r < nb ? r : nb - 1) * nb + ccl];
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = (t >> 6) + 4 * q;
+      Gs[r][cc] = (r < nb && cc < nb) ? g[q] : 0.0;
+    }
+  }
+  __syncthreads();
   if (t < 64) {
-    const int good = chol_factor(G, nb, c0, nrm0, dead, final, healthy, shift, dead_tol,
+    const int good = chol_factor(nb, c0, nrm0, dead, final, healthy, shift, dead_tol,
                                  blockIdx.x == 0, Rw, Gs, Rs);
     if (t == 0) good_s = good;
   }
@@ -1067,7 +1091,7 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
   double* nrm0 = (double*)c.arena.alloc(sizeof(double) * (size_t)kk);
   int* dead = (int*)c.arena.alloc(sizeof(int) * (size_t)kk);
   double* G = (double*)c.arena.alloc(sizeof(double) * (size_t)kk * OB);
-  double* Gb = (double*)c.arena.alloc(sizeof(double) * OB * OB);
+  double* Gp = (double*)c.arena.alloc(sizeof(double) * kMaxF64Splits * OB * OB);
   int* healthy = (int*)c.arena.alloc(sizeof(int));
   if (!c.dry) {
     ProfScope ps(c, K_SVD_OTHER, 0.0, 8.0 * (double)m * kk);
@@ -1086,17 +1110,17 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
       }
       // in-block: Cholesky QR of the block when it is well conditioned,
       // classical Gram-Schmidt twice otherwise (decided on the device)
-      gemm(c, F64, nbk, nbk, m, 1.0, A + c0, kk, 1, A + c0, kk, 0, 0.0, Gb, nbk);
+      const int gsplits = gemm_f64_partials(c, nbk, nbk, m, A + c0, kk, 1, A + c0, kk, 0, Gp);
       if (!c.dry) {
         const bool shifted = loose && pass == 0;
         // Cholesky nb^3 / 3 and triangular inverse nb^3 / 3 flop (once: the
-        // workgroups repeat it side by side), apply m nb^2; G in, the block
-        // read and written
+        // workgroups repeat it side by side), apply m nb^2; the slabs of G
+        // in, the block read and written
         const double b3 = (double)nbk * nbk * nbk;
         ProfScope ps(c, K_CHOL, 2.0 * b3 / 3.0 + (double)m * nbk * nbk,
-                     8.0 * ((double)nbk * nbk + 2.0 * m * nbk), 1, true);
-        launch(ps, chol_apply_kernel, dim3((m + 63) / 64), dim3(256), c.stream, (const double*)Gb,
-               nbk, c0, (const double*)nrm0, dead, loose ? 0 : pass, healthy,
+                     8.0 * ((double)gsplits * nbk * nbk + 2.0 * m * nbk), 1, true);
+        launch(ps, chol_apply_kernel, dim3((m + 63) / 64), dim3(256), c.stream, (const double*)Gp,
+               gsplits, nbk, c0, (const double*)nrm0, dead, loose ? 0 : pass, healthy,
                shifted ? 1e-12 : 0.0, dead_tol(), A, m, kk);
         c.check_launch();
       }
