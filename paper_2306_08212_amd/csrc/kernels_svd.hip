@@ -499,18 +499,22 @@ __device__ __forceinline__ double block_sum256(double v, double* sh) {
   return sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-__global__ __launch_bounds__(256) void tsqr_local_kernel(
+// LDS of one chunk of the Gram-Schmidt tree, in doubles: T[TQ][OBP], then
+// red[256 / OBW][OBP], coef[OBW] and sh[4].
+constexpr int TSQR_LDS = TQ * OBP + (256 / OBW) * OBP + OBW + 4;
+
+// One chunk (TQ rows from row chunk * TQ) of a level of the Gram-Schmidt
+// tree, run by a whole workgroup; L is TSQR_LDS doubles of LDS.
+__device__ __forceinline__ void tsqr_local_chunk(
     const double* __restrict__ src, int rows, int64_t lds, int nb, double* __restrict__ q,
     int64_t ldq, int qcols, double* __restrict__ r, int top, const double* __restrict__ nrm0,
-    int c0, int* __restrict__ dead, int final, const int* __restrict__ healthy, double dead_tol) {
-  __shared__ double T[TQ][OBP];
-  __shared__ double red[256 / OBW][OBP];
-  __shared__ double coef[OBW];
-  __shared__ double sh[4];
-  __shared__ int dep;
-  if (*healthy) return;   // the Cholesky path took this block
+    int c0, int* __restrict__ dead, int final, double dead_tol, int chunk, double* L, int& dep) {
+  double (*T)[OBP] = reinterpret_cast<double (*)[OBP]>(L);
+  double (*red)[OBP] = reinterpret_cast<double (*)[OBP]>(L + TQ * OBP);
+  double* coef = L + TQ * OBP + (256 / OBW) * OBP;
+  double* sh = coef + OBW;
   const int t = threadIdx.x;
-  const int i0 = blockIdx.x * TQ;
+  const int i0 = chunk * TQ;
   for (int e = t; e < TQ * OBW; e += 256) {
     const int rr = e / OBW, cc = e % OBW;
     T[rr][cc] = (i0 + rr < rows && cc < nb) ? src[(int64_t)(i0 + rr) * lds + cc] : 0.0;
@@ -557,7 +561,7 @@ __global__ __launch_bounds__(256) void tsqr_local_kernel(
   };
   auto put_r = [&](int j, double rjj) {
     if (r != nullptr && t < OBW)
-      r[((int64_t)blockIdx.x * OBW + t) * OBW + j] = t < j ? racc : (t == j ? rjj : 0.0);
+      r[((int64_t)chunk * OBW + t) * OBW + j] = t < j ? racc : (t == j ? rjj : 0.0);
     racc = 0.0;
   };
   for (int j = 0; j < nb; ++j) {
@@ -604,6 +608,19 @@ __global__ __launch_bounds__(256) void tsqr_local_kernel(
     const int rr = e / OBW, cc = e % OBW;
     if (i0 + rr < rows && cc < qcols) q[(int64_t)(i0 + rr) * ldq + cc] = T[rr][cc];
   }
+}
+
+// A level of the tree above the first (which the Cholesky kernel runs), one
+// chunk per workgroup, when the block was not healthy.
+__global__ __launch_bounds__(256) void tsqr_local_kernel(
+    const double* __restrict__ src, int rows, int64_t lds, int nb, double* __restrict__ q,
+    int64_t ldq, int qcols, double* __restrict__ r, int top, const double* __restrict__ nrm0,
+    int c0, int* __restrict__ dead, int final, const int* __restrict__ healthy, double dead_tol) {
+  __shared__ double L[TSQR_LDS];
+  __shared__ int dep;
+  if (*healthy) return;   // the Cholesky path took this block
+  tsqr_local_chunk(src, rows, lds, nb, q, ldq, qcols, r, top, nrm0, c0, dead, final, dead_tol,
+                   blockIdx.x, L, dep);
 }
 
 // dst rows of chunk b = Q rows of chunk b (TQ x OBW, ld OBW) times W rows
@@ -859,16 +876,29 @@ __device__ __forceinline__ int chol_factor(int nb, int c0, const double* __restr
 // 16-byte LDS words for sixteen FMAs.  R^{-1} is upper triangular, so a wave
 // stops at its last column; the products are summed in increasing inner
 // index, one accumulator per element.
+// The nfb workgroups after the (m + 63) / 64 of the apply run the first
+// level of the Gram-Schmidt fallback instead, chunk blockIdx.x - (m + 63) /
+// 64 each, when the block is not healthy (tsqr_local_chunk, arguments q0,
+// ldq0, qcols0, r0, top0; its later levels are launches of their own).  The
+// apply and the fallback never both run, so neither reads what the other
+// writes.
+constexpr int CHOL_LDS = 2 * OBW * OBP + 2 * OBW * RLD;
+static_assert(TSQR_LDS <= CHOL_LDS, "the fallback chunk fits in the Cholesky kernel's LDS");
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_apply_kernel(
     const double* __restrict__ Gp, int splits, int nb, int c0, const double* __restrict__ nrm0,
     int* __restrict__ dead, int final, int* __restrict__ healthy, double shift, double dead_tol,
-    double* __restrict__ U, int m, int kk) {
-  __shared__ double Rw[OBW][OBP];   // row j of the trailing matrix as it stood at step j
-  __shared__ double Gs[OBW][OBP];   // G, zero beyond nb
-  __shared__ double Rs[OBW][RLD];   // Rs[a][c] = R^{-1}[a][c]
-  __shared__ double Pt[OBW][RLD];   // Pt[a][r] = U[i0 + r][c0 + a]
-  __shared__ int good_s;
+    double* __restrict__ U, int m, int kk, double* __restrict__ q0, int64_t ldq0, int qcols0,
+    double* __restrict__ r0, int top0) {
+  __shared__ __align__(16) double L[CHOL_LDS];
+  // row j of the trailing matrix as it stood at step j
+  double (*Rw)[OBP] = reinterpret_cast<double (*)[OBP]>(L);
+  double (*Gs)[OBP] = reinterpret_cast<double (*)[OBP]>(L + OBW * OBP);   // G, zero beyond nb
+  // Rs[a][c] = R^{-1}[a][c]; Pt[a][r] = U[i0 + r][c0 + a]
+  double (*Rs)[RLD] = reinterpret_cast<double (*)[RLD]>(L + 2 * OBW * OBP);
+  double (*Pt)[RLD] = reinterpret_cast<double (*)[RLD]>(L + 2 * OBW * OBP + OBW * RLD);
+  __shared__ int good_s, dep_s;
   const int t = threadIdx.x;
+  const int napply = (m + 63) / 64;
   {
     // element (r, cc) = (t / 64 + 4 q, t % 64); clamped addresses, so every
     // load is issued and the values beyond nb are dropped
@@ -884,14 +914,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     } else {
 #pragma unroll
       for (int q = 0; q < 16; ++q) g[q] = 0.0;
-#pragma unroll 2
-      for (int z = 0; z < splits; ++z) {
-        const double* slab = Gp + z * nn;
+      // four slabs' loads in flight before their sums; a slab beyond the
+      // last adds 0.0, which leaves the sum bitwise as it is (it starts
+      // from +0.0, so it is never -0.0)
+      for (int z = 0; z < splits; z += 4) {
+        double v[4][16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int r = (t >> 6) + 4 * q;
-          g[q] += slab[(r < nb ? r : nb - 1) * nb + ccl];
+        for (int zz = 0; zz < 4; ++zz) {
+          const bool in = z + zz < splits;
+          const double* slab = Gp + (in ? z + zz : z) * nn;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) {
+            const int r = (t >> 6) + 4 * q;
+            v[zz][q] = slab[(r < nb ? r : nb - 1) * nb + ccl];
+            if (!in) v[zz][q] = 0.0;
+          }
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int zz = 0; zz < 4; ++zz)
+#pragma unroll
+          for (int q = 0; q < 16; ++q) g[q] += v[zz][q];
       }
     }
 #pragma unroll
@@ -907,7 +950,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     if (t == 0) good_s = good;
   }
   __syncthreads();
-  if (!good_s) return;
+  const int good = good_s;
+  if ((int)blockIdx.x >= napply) {
+    if (good) return;
+    tsqr_local_chunk(U + c0, m, kk, nb, q0, ldq0, qcols0, r0, top0, nrm0, c0, dead, final,
+                     dead_tol, blockIdx.x - napply, L, dep_s);
+    return;
+  }
+  if (!good) return;
   const int i0 = blockIdx.x * 64;
   double pv[16];
 #pragma unroll
@@ -1014,28 +1064,30 @@ __global__ void spec_finish_kernel(const double* __restrict__ S, int kk, int chi
 
 namespace {
 
-// The Gram-Schmidt tree for block [c0, c0 + nbk) of A (kernels exit at once
-// when the Cholesky path has taken the block).
+// The Gram-Schmidt tree for block [c0, c0 + nbk) of A above its first level,
+// which the Cholesky kernel runs into q0 (m x OBW, all OBW columns, zeros
+// beyond nbk) and r0 (one OBW x OBW factor per chunk of TQ rows); when m
+// fits one chunk that level was the whole tree and wrote A itself.  The
+// kernels exit at once when the Cholesky path has taken the block.
 void tsqr_fallback(Ctx& c, double* A, int m, int kk, int c0, int nbk, const double* nrm0,
-                   int* dead, int pass, const int* healthy) {
+                   int* dead, int pass, const int* healthy, double* q0, const double* r0) {
+  const int chunks0 = (m + TQ - 1) / TQ;
+  if (chunks0 == 1) return;
   const size_t mk = c.arena.mark();
-  const double* src = A + c0;
-  int64_t lds = kk;
-  int rows = m;
-  std::vector<double*> qs;
-  std::vector<int> rws;
+  const double* src = r0;
+  int64_t lds = OBW;
+  int rows = chunks0 * OBW;
+  std::vector<double*> qs{q0};
+  std::vector<int> rws{m};
   for (;;) {
     const int chunks = (rows + TQ - 1) / TQ;
     const bool top = chunks == 1;
-    double* q = top && qs.empty() ? A + c0 : (double*)c.arena.alloc(sizeof(double) * (size_t)rows * OBW);
-    const int64_t ldq = top && qs.empty() ? kk : OBW;
+    double* q = (double*)c.arena.alloc(sizeof(double) * (size_t)rows * OBW);
     double* r = top ? nullptr : (double*)c.arena.alloc(sizeof(double) * (size_t)chunks * OBW * OBW);
     if (!c.dry) {
       ProfScope ps(c, K_SVD_OTHER, 6.0 * rows * nbk * nbk, 8.0 * 2.0 * rows * nbk);
-      // scratch Q factors carry all OBW columns (zeros beyond nbk)
-      const int qcols = (q == A + c0) ? nbk : OBW;
       hipLaunchKernelGGL(tsqr_local_kernel, dim3(chunks), dim3(256), 0, c.stream, src, rows, lds,
-                         nbk, q, ldq, qcols, r, top ? 1 : 0, nrm0, c0, dead, pass, healthy,
+                         nbk, q, (int64_t)OBW, OBW, r, top ? 1 : 0, nrm0, c0, dead, pass, healthy,
                          dead_tol());
       c.check_launch();
     }
@@ -1093,6 +1145,12 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
   double* G = (double*)c.arena.alloc(sizeof(double) * (size_t)kk * OB);
   double* Gp = (double*)c.arena.alloc(sizeof(double) * kMaxF64Splits * OB * OB);
   int* healthy = (int*)c.arena.alloc(sizeof(int));
+  // the first level of the Gram-Schmidt fallback (run by the Cholesky
+  // kernel): Q and R factors of its chunks when there are several
+  const int chunks0 = (m + TQ - 1) / TQ;
+  double* q0 = chunks0 > 1 ? (double*)c.arena.alloc(sizeof(double) * (size_t)m * OB) : nullptr;
+  double* r0 =
+      chunks0 > 1 ? (double*)c.arena.alloc(sizeof(double) * (size_t)chunks0 * OB * OB) : nullptr;
   if (!c.dry) {
     ProfScope ps(c, K_SVD_OTHER, 0.0, 8.0 * (double)m * kk);
     hipLaunchKernelGGL(rm_colsq_kernel, dim3((kk + 255) / 256, chunks), dim3(256), 0, c.stream, A,
@@ -1119,12 +1177,17 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
         const double b3 = (double)nbk * nbk * nbk;
         ProfScope ps(c, K_CHOL, 2.0 * b3 / 3.0 + (double)m * nbk * nbk,
                      8.0 * ((double)gsplits * nbk * nbk + 2.0 * m * nbk), 1, true);
-        launch(ps, chol_apply_kernel, dim3((m + 63) / 64), dim3(256), c.stream, (const double*)Gp,
-               gsplits, nbk, c0, (const double*)nrm0, dead, loose ? 0 : pass, healthy,
-               shifted ? 1e-12 : 0.0, dead_tol(), A, m, kk);
+        // the shifted factorisation cannot fail: no fallback workgroups
+        const int nfb = shifted ? 0 : chunks0;
+        const bool one = chunks0 == 1;
+        launch(ps, chol_apply_kernel, dim3((m + 63) / 64 + nfb), dim3(256), c.stream,
+               (const double*)Gp, gsplits, nbk, c0, (const double*)nrm0, dead, loose ? 0 : pass,
+               healthy, shifted ? 1e-12 : 0.0, dead_tol(), A, m, kk, one ? A + c0 : q0,
+               (int64_t)(one ? kk : OB), one ? nbk : OB, r0, one ? 1 : 0);
         c.check_launch();
       }
-      if (!(loose && pass == 0)) tsqr_fallback(c, A, m, kk, c0, nbk, nrm0, dead, loose ? 0 : pass, healthy);
+      if (!(loose && pass == 0))
+        tsqr_fallback(c, A, m, kk, c0, nbk, nrm0, dead, loose ? 0 : pass, healthy, q0, r0);
     }
   }
   c.arena.release(mk);

@@ -127,7 +127,12 @@ SVD_CASES = [("square16", lambda: np.random.default_rng(0).standard_normal((16, 
               @ np.random.default_rng(5).standard_normal((5, 70)), 10),
              ("k>rank", lambda: np.random.default_rng(6).standard_normal((24, 24)), 64),
              ("tall256", lambda: _graded(512, 256, 0.97, 7), 256),
-             ("zerocols", lambda: _zero_cols(256, 256, 60, 150, 8), 64)]
+             ("zerocols", lambda: _zero_cols(256, 256, 60, 150, 8), 64),
+             # rank 30 over 96 columns of 1024 rows: dependent columns in
+             # every block of the QR, whose Gram-Schmidt fallback then spans
+             # four chunks of rows and a second level
+             ("tallrankdef", lambda: np.random.default_rng(9).standard_normal((1024, 30))
+              @ np.random.default_rng(10).standard_normal((30, 96)), 40)]
 
 
 @pytest.mark.parametrize("name,make,k", SVD_CASES)
