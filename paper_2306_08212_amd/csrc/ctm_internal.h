@@ -171,7 +171,9 @@ constexpr int kMaxF64Splits = 32;
 // z * m * n) holds the product over the z-th K range, and the sum of the
 // slabs in z order starting from 0.0 is gemm()'s result with alpha = 1,
 // beta = 0, bitwise.  With one slab part holds the product itself.  part has
-// room for kMaxF64Splits slabs.  Returns the number of slabs.
+// room for gemm_f64_split_count(m, n, k) slabs (at most kMaxF64Splits).
+// Returns the number of slabs.
+int gemm_f64_split_count(int m, int n, int k);
 int gemm_f64_partials(Ctx& c, int m, int n, int k, const double* A, int64_t lda, int ta,
                       const double* B, int64_t ldb, int tb, double* part);
 

@@ -378,6 +378,11 @@ int f64_splits(int m, int n, int k, int batch, int* kchunk) {
 
 }  // namespace
 
+int gemm_f64_split_count(int m, int n, int k) {
+  int kchunk = k;
+  return f64_splits(m, n, std::max(k, 0), 1, &kchunk);
+}
+
 int gemm_f64_partials(Ctx& c, int m, int n, int k, const double* A, int64_t lda, int ta,
                       const double* B, int64_t ldb, int tb, double* part) {
   if (m <= 0 || n <= 0) return 0;

@@ -610,35 +610,22 @@ __device__ __forceinline__ void tsqr_local_chunk(
   }
 }
 
-// A level of the tree above the first (which the Cholesky kernel runs), one
-// chunk per workgroup, when the block was not healthy.
-__global__ __launch_bounds__(256) void tsqr_local_kernel(
-    const double* __restrict__ src, int rows, int64_t lds, int nb, double* __restrict__ q,
-    int64_t ldq, int qcols, double* __restrict__ r, int top, const double* __restrict__ nrm0,
-    int c0, int* __restrict__ dead, int final, const int* __restrict__ healthy, double dead_tol) {
-  __shared__ double L[TSQR_LDS];
-  __shared__ int dep;
-  if (*healthy) return;   // the Cholesky path took this block
-  tsqr_local_chunk(src, rows, lds, nb, q, ldq, qcols, r, top, nrm0, c0, dead, final, dead_tol,
-                   blockIdx.x, L, dep);
-}
-
 // dst rows of chunk b = Q rows of chunk b (TQ x OBW, ld OBW) times W rows
 // [OBW b, OBW b + OBW) (ld OBW); nb columns.  The chunk's rows go through
-// LDS in two halves.
-__global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restrict__ Q, int rows,
-                                                         const double* __restrict__ W, int nb,
-                                                         double* __restrict__ dst, int64_t ldd,
-                                                         const int* __restrict__ healthy) {
+// LDS in two halves; L is LDS of at least OBW * OBP + (TQ / 2) * OBP
+// doubles.  Run by a whole workgroup.
+__device__ __forceinline__ void tsqr_apply_chunk(const double* __restrict__ Q, int rows,
+                                                 const double* __restrict__ W, int nb,
+                                                 double* __restrict__ dst, int64_t ldd, int b,
+                                                 double* L) {
   constexpr int TH = TQ / 2;
-  __shared__ double Ws[OBW][OBP];
-  __shared__ double Qs[TH][OBP];
-  if (*healthy) return;
+  double (*Ws)[OBP] = reinterpret_cast<double (*)[OBP]>(L);
+  double (*Qs)[OBP] = reinterpret_cast<double (*)[OBP]>(L + OBW * OBP);
   const int t = threadIdx.x;
   for (int e = t; e < OBW * OBW; e += 256)
-    Ws[e / OBW][e % OBW] = W[((int64_t)blockIdx.x * OBW + e / OBW) * OBW + e % OBW];
+    Ws[e / OBW][e % OBW] = W[((int64_t)b * OBW + e / OBW) * OBW + e % OBW];
   for (int h = 0; h < 2; ++h) {
-    const int i0 = blockIdx.x * TQ + h * TH;
+    const int i0 = b * TQ + h * TH;
     for (int e = t; e < TH * OBW; e += 256) {
       const int rr = e / OBW, cc = e % OBW;
       Qs[rr][cc] = (i0 + rr < rows) ? Q[(int64_t)(i0 + rr) * OBW + cc] : 0.0;
@@ -661,6 +648,71 @@ __global__ __launch_bounds__(256) void tsqr_apply_kernel(const double* __restric
         if (i0 + rr < rows) dst[(int64_t)(i0 + rr) * ldd + cc] = acc[q];
       }
     __syncthreads();
+  }
+}
+
+// The levels of the Gram-Schmidt tree above the first (which the Cholesky
+// kernel runs) and the products back down, for a block that was not
+// healthy.  Level l (1 <= l <= n) factors its input rows[l] x OBW (the
+// stacked R factors of level l - 1) chunk by chunk into q[l] and, below the
+// top level n, r[l]; then W_n = q[n], W_l = Q_l W_{l+1} into w[l] for
+// n > l >= 1, and the block of U = Q_0 W_1 with Q_0 = q[0].
+constexpr int kMaxTree = 8;
+struct TreeLevels {
+  int n;
+  int rows[kMaxTree + 1];
+  double* q[kMaxTree + 1];
+  double* r[kMaxTree + 1];
+  double* w[kMaxTree + 1];
+};
+static_assert(OBW * OBP + (TQ / 2) * OBP <= TSQR_LDS, "the apply's LDS fits the chunk's");
+
+// One launch with a workgroup per chunk of level 1, which exits at once when
+// the Cholesky path took the block.  The workgroups factor their chunks of
+// level 1; the last to finish (a device-scope counter, zeroed by the
+// Cholesky kernel; no workgroup waits for another) then runs the levels
+// above and the products down alone, one chunk after the other.  A
+// healthy block thus costs this one launch whatever the depth of the tree.
+__global__ __launch_bounds__(256) void tsqr_upper_kernel(TreeLevels tl, int nb,
+                                                         double* __restrict__ U, int64_t kk,
+                                                         int c0, const double* __restrict__ nrm0,
+                                                         int* __restrict__ dead, int final,
+                                                         const int* __restrict__ healthy,
+                                                         int* __restrict__ count,
+                                                         double dead_tol) {
+  __shared__ double L[TSQR_LDS];
+  __shared__ int dep, last;
+  if (*healthy) return;   // the Cholesky path took this block
+  const int t = threadIdx.x;
+  tsqr_local_chunk(tl.r[0], tl.rows[1], OBW, nb, tl.q[1], OBW, OBW, tl.r[1], tl.n == 1 ? 1 : 0,
+                   nrm0, c0, dead, final, dead_tol, blockIdx.x, L, dep);
+  if (gridDim.x > 1) {
+    __threadfence();   // this chunk's factors reach the device before the count
+    __syncthreads();
+    if (t == 0) last = atomicAdd(count, 1) == (int)gridDim.x - 1 ? 1 : 0;
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+  }
+  for (int l = 2; l <= tl.n; ++l) {
+    const int ch = (tl.rows[l] + TQ - 1) / TQ;
+    for (int b = 0; b < ch; ++b) {
+      __threadfence();
+      __syncthreads();
+      tsqr_local_chunk(tl.r[l - 1], tl.rows[l], OBW, nb, tl.q[l], OBW, OBW, tl.r[l],
+                       l == tl.n ? 1 : 0, nrm0, c0, dead, final, dead_tol, b, L, dep);
+    }
+  }
+  const double* W = tl.q[tl.n];
+  for (int l = tl.n - 1; l >= 0; --l) {
+    double* out = l == 0 ? U + c0 : tl.w[l];
+    const int ch = (tl.rows[l] + TQ - 1) / TQ;
+    for (int b = 0; b < ch; ++b) {
+      __threadfence();
+      __syncthreads();
+      tsqr_apply_chunk(tl.q[l], tl.rows[l], W, l == 0 ? nb : OBW, out, l == 0 ? kk : OBW, b, L);
+    }
+    W = out;
   }
 }
 
@@ -879,9 +931,9 @@ __device__ __forceinline__ int chol_factor(int nb, int c0, const double* __restr
 // The nfb workgroups after the (m + 63) / 64 of the apply run the first
 // level of the Gram-Schmidt fallback instead, chunk blockIdx.x - (m + 63) /
 // 64 each, when the block is not healthy (tsqr_local_chunk, arguments q0,
-// ldq0, qcols0, r0, top0; its later levels are launches of their own).  The
-// apply and the fallback never both run, so neither reads what the other
-// writes.
+// ldq0, qcols0, r0, top0; its later levels are a launch of their own, whose
+// counter, healthy[1], the first workgroup zeroes).  The apply and the
+// fallback never both run, so neither reads what the other writes.
 constexpr int CHOL_LDS = 2 * OBW * OBP + 2 * OBW * RLD;
 static_assert(TSQR_LDS <= CHOL_LDS, "the fallback chunk fits in the Cholesky kernel's LDS");
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void chol_apply_kernel(
@@ -951,6 +1003,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   }
   __syncthreads();
   const int good = good_s;
+  if (blockIdx.x == 0 && t == 0) healthy[1] = 0;   // the fallback's counter
   if ((int)blockIdx.x >= napply) {
     if (good) return;
     tsqr_local_chunk(U + c0, m, kk, nb, q0, ldq0, qcols0, r0, top0, nrm0, c0, dead, final,
@@ -1067,49 +1120,45 @@ namespace {
 // The Gram-Schmidt tree for block [c0, c0 + nbk) of A above its first level,
 // which the Cholesky kernel runs into q0 (m x OBW, all OBW columns, zeros
 // beyond nbk) and r0 (one OBW x OBW factor per chunk of TQ rows); when m
-// fits one chunk that level was the whole tree and wrote A itself.  The
-// kernels exit at once when the Cholesky path has taken the block.
+// fits one chunk that level was the whole tree and wrote A itself.  One
+// launch (tsqr_upper_kernel), which exits at once when the Cholesky path has
+// taken the block; count is its counter, zeroed by the Cholesky kernel.
 void tsqr_fallback(Ctx& c, double* A, int m, int kk, int c0, int nbk, const double* nrm0,
-                   int* dead, int pass, const int* healthy, double* q0, const double* r0) {
+                   int* dead, int pass, const int* healthy, double* q0, double* r0, int* count) {
   const int chunks0 = (m + TQ - 1) / TQ;
   if (chunks0 == 1) return;
   const size_t mk = c.arena.mark();
-  const double* src = r0;
-  int64_t lds = OBW;
-  int rows = chunks0 * OBW;
-  std::vector<double*> qs{q0};
-  std::vector<int> rws{m};
+  TreeLevels tl{};
+  tl.rows[0] = m;
+  tl.q[0] = q0;
+  tl.r[0] = r0;
+  int rows = chunks0 * OBW, n = 0;
   for (;;) {
+    if (++n > kMaxTree) throw Error(1, "orthonormalize: too many rows");   // bad argument
     const int chunks = (rows + TQ - 1) / TQ;
-    const bool top = chunks == 1;
-    double* q = (double*)c.arena.alloc(sizeof(double) * (size_t)rows * OBW);
-    double* r = top ? nullptr : (double*)c.arena.alloc(sizeof(double) * (size_t)chunks * OBW * OBW);
-    if (!c.dry) {
-      ProfScope ps(c, K_SVD_OTHER, 6.0 * rows * nbk * nbk, 8.0 * 2.0 * rows * nbk);
-      hipLaunchKernelGGL(tsqr_local_kernel, dim3(chunks), dim3(256), 0, c.stream, src, rows, lds,
-                         nbk, q, (int64_t)OBW, OBW, r, top ? 1 : 0, nrm0, c0, dead, pass, healthy,
-                         dead_tol());
-      c.check_launch();
-    }
-    qs.push_back(q);
-    rws.push_back(rows);
-    if (top) break;
-    src = r;
-    lds = OBW;
+    tl.rows[n] = rows;
+    tl.q[n] = (double*)c.arena.alloc(sizeof(double) * (size_t)rows * OBW);
+    tl.r[n] = chunks == 1 ? nullptr
+                          : (double*)c.arena.alloc(sizeof(double) * (size_t)chunks * OBW * OBW);
+    if (chunks == 1) break;
     rows = chunks * OBW;
   }
-  // multiply back down: W_l = Q_l W_{l+1}; the last product lands in A
-  const double* W = qs.back();
-  for (int l = (int)qs.size() - 2; l >= 0; --l) {
-    double* out = (l == 0) ? A + c0 : (double*)c.arena.alloc(sizeof(double) * (size_t)rws[l] * OBW);
-    const int64_t ldo = (l == 0) ? kk : OBW;
-    if (!c.dry) {
-      ProfScope ps(c, K_SVD_OTHER, 2.0 * rws[l] * (double)OBW * nbk, 8.0 * 3.0 * rws[l] * OBW);
-      hipLaunchKernelGGL(tsqr_apply_kernel, dim3((rws[l] + TQ - 1) / TQ), dim3(256), 0, c.stream,
-                         qs[l], rws[l], W, (l == 0) ? nbk : OBW, out, ldo, healthy);
-      c.check_launch();
+  tl.n = n;
+  for (int l = 1; l < n; ++l)
+    tl.w[l] = (double*)c.arena.alloc(sizeof(double) * (size_t)tl.rows[l] * OBW);
+  if (!c.dry) {
+    // the tree's work when it runs: Gram-Schmidt twice over each level and
+    // the products down; it is timed whether or not it runs
+    double fl = 0.0, by = 0.0;
+    for (int l = 1; l <= n; ++l) fl += 6.0 * tl.rows[l] * (double)nbk * nbk;
+    for (int l = 0; l < n; ++l) {
+      fl += 2.0 * tl.rows[l] * (double)OBW * nbk;
+      by += 8.0 * 3.0 * tl.rows[l] * OBW;
     }
-    W = out;
+    ProfScope ps(c, K_SVD_OTHER, fl, by);
+    hipLaunchKernelGGL(tsqr_upper_kernel, dim3((tl.rows[1] + TQ - 1) / TQ), dim3(256), 0, c.stream,
+                       tl, nbk, A, (int64_t)kk, c0, nrm0, dead, pass, healthy, count, dead_tol());
+    c.check_launch();
   }
   c.arena.release(mk);
 }
@@ -1143,8 +1192,11 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
   double* nrm0 = (double*)c.arena.alloc(sizeof(double) * (size_t)kk);
   int* dead = (int*)c.arena.alloc(sizeof(int) * (size_t)kk);
   double* G = (double*)c.arena.alloc(sizeof(double) * (size_t)kk * OB);
-  double* Gp = (double*)c.arena.alloc(sizeof(double) * kMaxF64Splits * OB * OB);
-  int* healthy = (int*)c.arena.alloc(sizeof(int));
+  // the block Gram's split-K slabs (the split depends on m alone: every
+  // block has the same K = m and at most OB columns)
+  const int gslabs = gemm_f64_split_count(OB, OB, m);
+  double* Gp = (double*)c.arena.alloc(sizeof(double) * (size_t)gslabs * OB * OB);
+  int* healthy = (int*)c.arena.alloc(sizeof(int) * 2);   // and the fallback's counter
   // the first level of the Gram-Schmidt fallback (run by the Cholesky
   // kernel): Q and R factors of its chunks when there are several
   const int chunks0 = (m + TQ - 1) / TQ;
@@ -1169,6 +1221,7 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
       // in-block: Cholesky QR of the block when it is well conditioned,
       // classical Gram-Schmidt twice otherwise (decided on the device)
       const int gsplits = gemm_f64_partials(c, nbk, nbk, m, A + c0, kk, 1, A + c0, kk, 0, Gp);
+      if (gsplits > gslabs) throw Error(2, "orthonormalize: Gram slabs beyond their buffer");
       if (!c.dry) {
         const bool shifted = loose && pass == 0;
         // Cholesky nb^3 / 3 and triangular inverse nb^3 / 3 flop (once: the
@@ -1187,7 +1240,8 @@ void orthonormalize(Ctx& c, double* A, int m, int kk, int rounds = 2) {
         c.check_launch();
       }
       if (!(loose && pass == 0))
-        tsqr_fallback(c, A, m, kk, c0, nbk, nrm0, dead, loose ? 0 : pass, healthy, q0, r0);
+        tsqr_fallback(c, A, m, kk, c0, nbk, nrm0, dead, loose ? 0 : pass, healthy, q0, r0,
+                      healthy + 1);
     }
   }
   c.arena.release(mk);

@@ -132,7 +132,11 @@ SVD_CASES = [("square16", lambda: np.random.default_rng(0).standard_normal((16, 
              # every block of the QR, whose Gram-Schmidt fallback then spans
              # four chunks of rows and a second level
              ("tallrankdef", lambda: np.random.default_rng(9).standard_normal((1024, 30))
-              @ np.random.default_rng(10).standard_normal((30, 96)), 40)]
+              @ np.random.default_rng(10).standard_normal((30, 96)), 40),
+             # 4096 rows: four chunks at the tree's second level, whose last
+             # workgroup to finish runs the third level and the products down
+             ("tallrankdef4096", lambda: np.random.default_rng(11).standard_normal((4096, 30))
+              @ np.random.default_rng(12).standard_normal((30, 96)), 40)]
 
 
 @pytest.mark.parametrize("name,make,k", SVD_CASES)
