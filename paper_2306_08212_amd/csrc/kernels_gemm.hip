@@ -128,8 +128,17 @@ __global__ __launch_bounds__(256) void gemm_f64_splitk_sum(int M, int N, int bat
   const int64_t per = (int64_t)M * N, total = per * batch;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * 256) {
+    // eight slabs' loads in flight, summed in z order
     double acc = 0.0;
-    for (int z = 0; z < splits; ++z) acc += part[(int64_t)z * total + e];
+    int z = 0;
+    for (; z + 8 <= splits; z += 8) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(z + u) * total + e];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; z < splits; ++z) acc += part[(int64_t)z * total + e];
     const int64_t bz = e / per, r = e % per;
     const int gm = (int)(r / N), gn = (int)(r % N);
     double* cp = C + sC * bz + (int64_t)gm * ldc + gn;

@@ -374,8 +374,17 @@ __global__ __launch_bounds__(256) void rm_colsq_kernel(const double* __restrict_
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= n) return;
   const int i0 = blockIdx.y * rows, i1 = min(m, i0 + rows);
+  // sixteen loads in flight, then their squares summed in row order
   double s = 0.0;
-  for (int i = i0; i < i1; ++i) {
+  int i = i0;
+  for (; i + 16 <= i1; i += 16) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) v[u] = M[(int64_t)(i + u) * n + j];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s += v[u] * v[u];
+  }
+  for (; i < i1; ++i) {
     const double v = M[(int64_t)i * n + j];
     s += v * v;
   }
@@ -388,7 +397,15 @@ __global__ __launch_bounds__(256) void rm_colnorm_kernel(const double* __restric
   const int j = blockIdx.x * 256 + threadIdx.x;
   if (j >= n) return;
   double s = 0.0;
-  for (int q = 0; q < chunks; ++q) s += part[(int64_t)q * n + j];
+  int q = 0;
+  for (; q + 8 <= chunks; q += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(q + u) * n + j];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
+  }
+  for (; q < chunks; ++q) s += part[(int64_t)q * n + j];
   sig[j] = sqrt(s);
 }
 
@@ -431,16 +448,33 @@ __global__ __launch_bounds__(256) void jac_colnorm_kernel(const double* __restri
 // whatever the data: the indices feed gathers.
 __global__ __launch_bounds__(256) void jac_rank_kernel(const double* __restrict__ sig, int c, int kk,
                                                        int* __restrict__ order) {
+  // the keys pass through LDS 1024 at a time; each thread counts the keys
+  // that precede its own
+  __shared__ double ks[1024];
   const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= c) return;
   auto key = [](double x) { return x == x ? x : -INFINITY; };
-  const double v = key(sig[j]);
+  const double v = j < c ? key(sig[j]) : 0.0;
   int rank = 0;
-  for (int i = 0; i < c; ++i) {
-    const double w = key(sig[i]);
-    rank += (w > v) || (w == v && i < j);
+  for (int i0 = 0; i0 < c; i0 += 1024) {
+    const int n = min(1024, c - i0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < n; e += 256) ks[e] = key(sig[i0 + e]);
+    __syncthreads();
+    int r4[4] = {0, 0, 0, 0};
+    int e = 0;
+    for (; e + 4 <= n; e += 4)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double w = ks[e + u];
+        r4[u] += (w > v) || (w == v && i0 + e + u < j);
+      }
+    for (; e < n; ++e) {
+      const double w = ks[e];
+      r4[0] += (w > v) || (w == v && i0 + e < j);
+    }
+    rank += (r4[0] + r4[1]) + (r4[2] + r4[3]);
   }
-  if (rank < kk) order[rank] = j;
+  if (j < c && rank < kk) order[rank] = j;
 }
 
 // Uj[:, t] (row-major vr x kk) = column order[t] of the accumulated
