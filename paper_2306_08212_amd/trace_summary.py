@@ -36,20 +36,38 @@ def _name(row):
 
 
 def load(d):
+    """(start, end, kernel name, stream) per dispatch, by start time; the
+    stream is the trace's Stream_Id, else its Queue_Id, else 0."""
     paths = glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)
     if not paths:
         raise SystemExit(f"no kernel_trace.csv under {d}")
     ev = []
     with open(paths[0]) as f:
         for r in csv.DictReader(f):
-            ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _name(r)))
+            sid = r.get("Stream_Id") or r.get("Queue_Id") or "0"
+            ev.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), _name(r), sid))
     ev.sort()
     return ev
 
 
+def busy_ms(ev):
+    """Time in ms during which at least one of the dispatches runs."""
+    tot, cur_s, cur_e = 0, None, None
+    for s, e, *_ in ev:
+        if cur_e is None or s > cur_e:
+            if cur_e is not None:
+                tot += cur_e - cur_s
+            cur_s, cur_e = s, e
+        else:
+            cur_e = max(cur_e, e)
+    if cur_e is not None:
+        tot += cur_e - cur_s
+    return tot / 1e6
+
+
 def table(ev, div=1.0, top=25):
     tot = collections.defaultdict(lambda: [0, 0.0])
-    for s, e, n in ev:
+    for s, e, n, _ in ev:
         tot[n][0] += 1
         tot[n][1] += (e - s) / 1e6
     allms = sum(v[1] for v in tot.values()) or 1.0
@@ -73,7 +91,7 @@ def main(argv=None):
     print("### Whole run\n\n" + hdr)
     print("\n".join(rows))
 
-    gates = [i for i, (s, e, n) in enumerate(ev) if n == "prof_gate_kernel"]
+    gates = [i for i, x in enumerate(ev) if x[2] == "prof_gate_kernel"]
     if not gates:
         print("\n(no gate kernels: the run has no profiled pass)")
         return 0
@@ -101,6 +119,16 @@ def main(argv=None):
               f"{ksum:.1f} ms per move; {len(win) / a.steps:.0f} launches per move.\n")
         print("| kernel | launches per move | ms per move | avg us | % |\n|---|---:|---:|---:|---:|")
         print("\n".join(rows))
+        # how much of the window the GPU and each stream spend running kernels
+        streams = collections.defaultdict(list)
+        for x in win:
+            streams[x[3]].append(x)
+        print(f"\nAt least one kernel running: {busy_ms(win) / a.steps:.1f} ms of the "
+              f"{wall / a.steps:.1f} ms per move.\n")
+        print("| stream | launches per move | busy ms per move | % of the window |\n|---|---:|---:|---:|")
+        for sid, xs in sorted(streams.items(), key=lambda kv: -len(kv[1])):
+            b = busy_ms(xs)
+            print(f"| {sid} | {len(xs) / a.steps:.0f} | {b / a.steps:.1f} | {100 * b / wall:.0f} |")
 
     rows, tot = table(prof, div=max(a.profiled, 1))
     print(f"\n### Profiled pass ({a.profiled} moves, gate kernels excluded)\n")
