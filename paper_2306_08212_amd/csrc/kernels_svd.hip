@@ -504,9 +504,10 @@ __global__ __launch_bounds__(256) void jac_pick_kernel(const double* __restrict_
 
 // Gram-Schmidt fallback of the in-block step, as a tree (TSQR): the block's
 // rows are cut into chunks of 256; each workgroup orthonormalises its chunk in
-// LDS (classical Gram-Schmidt twice, then a third projection that checks the
-// normalised column: if it loses more than half its length, the column was
-// rounding noise and is dependent), keeping the projection coefficients as
+// LDS (classical Gram-Schmidt twice, then, for a column that lost more than
+// half its length in those projections, a third projection that checks the
+// normalised column: if it loses more than half its length again, the column
+// was rounding noise and is dependent), keeping the projection coefficients as
 // the chunk's R factor.  The stacked R factors are reduced the same way until
 // one chunk is left; the Q factors are then multiplied back down the tree.
 // Zero columns of a Q factor come with zero rows of its R factor, so the
@@ -622,14 +623,22 @@ __device__ __forceinline__ void tsqr_local_chunk(
     if (!dep) {
       if (t < TQ) T[t][j] *= i1;
       __syncthreads();
-      project(j, r1);
-      const double q2 = colsq(j);
-      if (t == 0) dep = (q2 > 0.25) ? 0 : 1;
-      __syncthreads();
-      if (!dep) {
-        const double i2 = rsq_nr(q2);
-        if (t < TQ) T[t][j] *= i2;
-        rjj = r1 * (q2 * i2);
+      if (q1 >= 0.25 * q0) {
+        // the column kept at least half its norm through the two
+        // projections: it is orthogonal to the earlier ones to working
+        // accuracy already ("twice is enough"), and a third projection
+        // would only move it by rounding
+        rjj = r1;
+      } else {
+        project(j, r1);
+        const double q2 = colsq(j);
+        if (t == 0) dep = (q2 > 0.25) ? 0 : 1;
+        __syncthreads();
+        if (!dep) {
+          const double i2 = rsq_nr(q2);
+          if (t < TQ) T[t][j] *= i2;
+          rjj = r1 * (q2 * i2);
+        }
       }
     }
     if (dep && t < TQ) T[t][j] = 0.0;
