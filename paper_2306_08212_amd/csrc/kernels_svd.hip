@@ -203,24 +203,28 @@ __device__ void lds_sym_jacobi(double (*G)[JP + 1], double (*J)[JP + 1], double 
 // k = l/16; result lane l, element i is row l/16 + 4 i, column l%16).
 constexpr int CH = 64;
 
-__global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, int r, int64_t ldx,
-                                                        double* __restrict__ V, int vr, int nb,
-                                                        int round, double tol, double tol_in,
-                                                        int inner_sweeps,
-                                                        const double* __restrict__ fro,
-                                                        int* __restrict__ flags,
-                                                        double* __restrict__ work, int xslot,
-                                                        double thr_mult) {
-  __shared__ double G[JP][JP + 1];
-  __shared__ double J[JP][JP + 1];
-  __shared__ double chunk[CH][JP + 1];
-  __shared__ double outc[CH][JP + 1];
-  __shared__ int any, sflag;
-  // workgroups go to the 8 XCDs round robin; only those of XCD xslot work,
-  // so every round of one SVD finds X and V in the same L2
-  if ((int)(blockIdx.x & 7) != xslot) return;
-  const int pair = blockIdx.x >> 3;
-  if (flags[0]) return;   // converged in an earlier sweep
+// LDS of one block pair's step.
+struct JacLds {
+  double G[JP][JP + 1];
+  double J[JP][JP + 1];
+  double chunk[CH][JP + 1];
+  double outc[CH][JP + 1];
+  int any, sflag;
+};
+
+// The step of one block pair (pair of round `round`), run by a whole
+// workgroup.
+__device__ __forceinline__ void jac_pair(double* __restrict__ X, int r, int64_t ldx,
+                                         double* __restrict__ V, int vr, int nb, int round,
+                                         int pair, double tol, double tol_in, int inner_sweeps,
+                                         const double* __restrict__ fro, int* __restrict__ flags,
+                                         double* __restrict__ work, double thr_mult, JacLds& L) {
+  double (*G)[JP + 1] = L.G;
+  double (*J)[JP + 1] = L.J;
+  double (*chunk)[JP + 1] = L.chunk;
+  double (*outc)[JP + 1] = L.outc;
+  int& any = L.any;
+  int& sflag = L.sflag;
   // columns below the rounding noise of the rotations (norm < 2 sqrt(r) eps
   // ||M||_F) are not made orthogonal: their directions are not determined by
   // the data, and chasing them only spins through sweeps
@@ -332,6 +336,63 @@ __global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, 
       const int a = e / CH, rr = e % CH;
       if (row0 + rr < rows) dst[(int64_t)col(a) * ld + row0 + rr] = outc[rr][a];
     }
+  }
+}
+
+__global__ __launch_bounds__(256) void jac_round_kernel(double* __restrict__ X, int r, int64_t ldx,
+                                                        double* __restrict__ V, int vr, int nb,
+                                                        int round, double tol, double tol_in,
+                                                        int inner_sweeps,
+                                                        const double* __restrict__ fro,
+                                                        int* __restrict__ flags,
+                                                        double* __restrict__ work, int xslot,
+                                                        double thr_mult) {
+  __shared__ JacLds L;
+  // workgroups go to the 8 XCDs round robin; only those of XCD xslot work,
+  // so every round of one SVD finds X and V in the same L2
+  if ((int)(blockIdx.x & 7) != xslot) return;
+  if (flags[0]) return;   // converged in an earlier sweep
+  jac_pair(X, r, ldx, V, vr, nb, round, blockIdx.x >> 3, tol, tol_in, inner_sweeps, fro, flags,
+           work, thr_mult, L);
+}
+
+// The sweeps after the first few, in one launch of one workgroup, which
+// returns at once when the sweeps have converged (nearly always: the
+// preconditioned sweeps converge in at most about six).  Otherwise it takes
+// the remaining sweeps' block pairs one after the other, in the order the
+// rounds take them (every pair of a round is disjoint from the others, so
+// the order within a round does not change the result), and ends each sweep
+// as jac_sweep_end does.
+__global__ __launch_bounds__(256) void jac_late_kernel(double* __restrict__ X, int r, int64_t ldx,
+                                                       double* __restrict__ V, int vr, int nb,
+                                                       double tol, double tol_in, int inner_sweeps,
+                                                       const double* __restrict__ fro,
+                                                       int* __restrict__ flags,
+                                                       double* __restrict__ work,
+                                                       double thr_mult, int sweeps) {
+  __shared__ JacLds L;
+  __shared__ int done;
+  const int t = threadIdx.x;
+  for (int sw = 0; sw < sweeps; ++sw) {
+    if (t == 0) done = flags[0];
+    __syncthreads();
+    if (done) return;
+    for (int rd = 0; rd < nb - 1; ++rd)
+      for (int p = 0; p < nb / 2; ++p) {
+        jac_pair(X, r, ldx, V, vr, nb, rd, p, tol, tol_in, inner_sweeps, fro, flags, work,
+                 thr_mult, L);
+        // this pair's columns of X and V, and its count, before the next
+        // pair reads them
+        __threadfence();
+        __syncthreads();
+      }
+    if (t == 0) {
+      if (flags[0] == 0 && flags[1] == 0) flags[0] = 1;
+      if (flags[0] == 0) flags[2] += 1;
+      flags[1] = 0;
+    }
+    __threadfence();
+    __syncthreads();
   }
 }
 
@@ -1392,7 +1453,13 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
     // XCD of this SVD's Jacobi rounds (concurrent SVDs have their buffers
     // megabytes apart, so they mostly land on different XCDs)
     const int xslot = (int)(((uintptr_t)X >> 20) & 7);
-    for (int sw = 0; sw < max_sweeps; ++sw) {
+    // the first sweeps one launch per round; the rest, which converged
+    // sweeps make no-ops, in one launch (CTM_DEBUG_PAR_SWEEPS moves the split
+    // for the tests of that launch)
+    int par_sweeps = 8;
+    if (const char* ps = std::getenv("CTM_DEBUG_PAR_SWEEPS")) par_sweeps = std::max(1, std::atoi(ps));
+    par_sweeps = std::min(par_sweeps, max_sweeps);
+    for (int sw = 0; sw < par_sweeps; ++sw) {
       for (int rd = 0; rd < nb - 1; ++rd) {
         // each round timed by its own dispatch; its work is data dependent,
         // so the kernel tallies it on the device
@@ -1402,6 +1469,12 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
                thr_mult);
       }
       hipLaunchKernelGGL(jac_sweep_end, dim3(1), dim3(1), 0, c.stream, flags);
+    }
+    if (max_sweeps > par_sweeps) {
+      ProfScope ps(c, K_SVD_ROUND, 0.0, 0.0, 1, true);
+      launch(ps, jac_late_kernel, dim3(1), dim3(256), c.stream, X, r, (int64_t)r, V, n, nb, tol,
+             tol_in, inner_sweeps, fro, flags, c.prof ? c.work : nullptr, thr_mult,
+             max_sweeps - par_sweeps);
     }
     if (c.dev_flags)
       hipLaunchKernelGGL(jac_converged_check, dim3(1), dim3(1), 0, c.stream, flags, c.dev_flags);

@@ -235,3 +235,23 @@ def test_tsvd_reports_nonconvergence(monkeypatch):
     U, S = tsvd(M, 50)
     So = np.linalg.svd(M, compute_uv=False)[:50]
     np.testing.assert_allclose(S, So, rtol=0, atol=1e-12 * So[0])
+
+
+@pytest.mark.parametrize("name", ["graded", "tall256", "zerocols", "tallrankdef"])
+def test_tsvd_late_sweeps_in_one_launch(name, monkeypatch):
+    """The Jacobi sweeps after the first eight run in one launch of one
+    workgroup, block pair after block pair.  With the split moved to after
+    the first sweep (CTM_DEBUG_PAR_SWEEPS=1) every later sweep runs there;
+    the pairs of a round touch disjoint columns, so the result is bitwise the
+    one of the launch-per-round sweeps, and it still matches the oracle."""
+    make, k = {n: (mk, kk) for n, mk, kk in SVD_CASES}[name]
+    M = make()
+    log("tsvd late sweeps", name)
+    U0, S0 = tsvd(M, k)
+    monkeypatch.setenv("CTM_DEBUG_PAR_SWEEPS", "1")
+    U1, S1 = tsvd(M, k)
+    monkeypatch.delenv("CTM_DEBUG_PAR_SWEEPS")
+    assert np.array_equal(S0, S1)
+    assert np.array_equal(U0, U1)
+    So = O.truncate(M, k)[1]
+    np.testing.assert_allclose(S1, So, rtol=0, atol=1e-12 * So[0])
