@@ -91,7 +91,8 @@ def test_warm_started_request_matches_oracle():
     assert abs(cold.e_site - res.e_site) > 1e-12
 
 
-@pytest.mark.parametrize("D,chi,prec", [(3, 31, 1), (3, 17, 0), (4, 40, 1)])
+@pytest.mark.parametrize("D,chi,prec", [(3, 31, 1), (3, 17, 0), (4, 40, 1), (5, 43, 1),
+                                        (8, 184, 1), (7, 93, 1)])
 def test_results_do_not_depend_on_workspace_contents(D, chi, prec):
     """The same solve on a workspace holding zeros, NaN bit patterns or
     random bytes gives bitwise the same energies: no kernel reads memory
@@ -123,7 +124,8 @@ def test_results_do_not_depend_on_workspace_contents(D, chi, prec):
 
 
 @pytest.mark.parametrize("D,chi,prec,method", [(3, 31, 1, 1), (8, 65, 1, 1), (6, 120, 1, 1),
-                                               (4, 40, 0, 2), (3, 17, 2, 0)])
+                                               (4, 40, 0, 2), (3, 17, 2, 0), (5, 43, 1, 1),
+                                               (8, 184, 1, 1), (7, 93, 1, 1), (7, 184, 1, 1)])
 def test_no_write_past_the_workspace(D, chi, prec, method):
     """A solve (iterations, energy, observables) writes nothing beyond the
     workspace it was given: a guard region after it, filled with a
@@ -152,7 +154,8 @@ def test_no_write_past_the_workspace(D, chi, prec, method):
 
 
 @pytest.mark.parametrize("D,chi,prec,method", [(3, 31, 1, 1), (6, 120, 1, 1), (8, 65, 1, 1),
-                                               (4, 40, 0, 2), (3, 17, 2, 0)])
+                                               (4, 40, 0, 2), (3, 17, 2, 0), (5, 43, 1, 1),
+                                               (8, 184, 1, 1), (7, 93, 1, 1), (7, 184, 1, 1)])
 def test_branches_stay_inside_their_workspace_slices(D, chi, prec, method, monkeypatch):
     """The concurrent branches of a move each get a slice of the workspace.
     With CTM_DEBUG_GUARD set, every slice is followed by a sentinel region
