@@ -1026,7 +1026,9 @@ __device__ __forceinline__ int chol_factor(int nb, int c0, const double* __restr
 // first wave factors G (every workgroup the same arithmetic on the same G,
 // so the same R^{-1} and verdict; the first workgroup records them), which
 // costs no time over one factorisation and saves a launch and a round trip
-// of R^{-1} through memory.  Apply: the rows (transposed) sit in LDS next to
+// of R^{-1} through memory.  While the first wave factors, the other three
+// stage the workgroup's rows of the block in LDS.  Apply: the rows
+// (transposed) sit in LDS next to
 // R^{-1}, and each thread forms a 4 x 4 tile of the product, wave w the
 // columns 16 w .. 16 w + 15, so a step over the inner index reads four
 // 16-byte LDS words for sixteen FMAs.  R^{-1} is upper triangular, so a wave
@@ -1100,10 +1102,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     }
   }
   __syncthreads();
+  const int i0 = blockIdx.x * 64;
   if (t < 64) {
     const int good = chol_factor(nb, c0, nrm0, dead, final, healthy, shift, dead_tol,
                                  blockIdx.x == 0, Rw, Gs, Rs);
     if (t == 0) good_s = good;
+  } else if ((int)blockIdx.x < napply) {
+    // meanwhile the other three waves stage the workgroup's rows of the block,
+    // transposed: Pt[a][r] = U[i0 + r][c0 + a] (zero beyond m and nb)
+    constexpr int PQ = (64 * OBW + 191) / 192;
+    double pv[PQ];
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int e = (t - 64) + 192 * q;
+      const int r = e >> 6, cc = e & 63;
+      pv[q] = (e < 64 * OBW && i0 + r < m && cc < nb) ? U[(int64_t)(i0 + r) * kk + c0 + cc] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < PQ; ++q) {
+      const int e = (t - 64) + 192 * q;
+      if (e < 64 * OBW) Pt[e & 63][e >> 6] = pv[q];
+    }
   }
   __syncthreads();
   const int good = good_s;
@@ -1115,19 +1134,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     return;
   }
   if (!good) return;
-  const int i0 = blockIdx.x * 64;
-  double pv[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int r = (t >> 6) + 4 * q, cc = t & 63;
-    pv[q] = (i0 + r < m && cc < nb) ? U[(int64_t)(i0 + r) * kk + c0 + cc] : 0.0;
-  }
-#pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int r = (t >> 6) + 4 * q, cc = t & 63;
-    Pt[cc][r] = pv[q];
-  }
-  __syncthreads();
   const int w = t >> 6, lane = t & 63;
   const int rb = (lane >> 2) * 4, cb = w * 16 + (lane & 3) * 4;
   const int amax = min(nb, w * 16 + 16);   // R^{-1}[a][c] = 0 for a > c
