@@ -166,11 +166,10 @@ void gemm(Ctx& c, int dtype, int m, int n, int k, double alpha, const void* A,
 // Most K slabs an FP64 product is split into.
 constexpr int kMaxF64Splits = 32;
 
-// The FP64 product op(A) op(B) (m x n, row-major) over K split as gemm()
-// splits it, for a consumer that sums the slabs itself: slab z of part (at
-// z * m * n) holds the product over the z-th K range, and the sum of the
-// slabs in z order starting from 0.0 is gemm()'s result with alpha = 1,
-// beta = 0, bitwise.  With one slab part holds the product itself.  part has
+// The FP64 product op(A) op(B) (m x n, row-major) over K split into slabs
+// of at least 128 (gemm() takes 64), for a consumer that sums the slabs
+// itself: slab z of part (at z * m * n) holds the product over the z-th K
+// range.  With one slab part holds the product itself.  part has
 // room for gemm_f64_split_count(m, n, k) slabs (at most kMaxF64Splits).
 // Returns the number of slabs.
 int gemm_f64_split_count(int m, int n, int k);

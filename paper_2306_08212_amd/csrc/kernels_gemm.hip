@@ -373,13 +373,16 @@ __global__ __launch_bounds__(256) void gemm_bf16_kernel(
 }
 
 // K split of an FP64 product whose grid cannot fill the chip: the number of
-// slabs (1: none) and the K extent of each.
-int f64_splits(int m, int n, int k, int batch, int* kchunk) {
+// slabs (1: none) and the K extent of each, at least kmin.  These products
+// are short latency chains per workgroup, so slabs of 64 (two K tiles) make
+// them fastest; the block Grams of the QR steps take 128, because every
+// workgroup of the Cholesky kernel sums all their slabs.
+int f64_splits(int m, int n, int k, int batch, int* kchunk, int kmin = 64) {
   *kchunk = k;
   const int64_t tiles = (int64_t)((m + F64_BM - 1) / F64_BM) * ((n + F64_BN - 1) / F64_BN) * batch;
   if (tiles >= 256 || k < 256) return 1;
   int64_t want = (512 + tiles - 1) / tiles;
-  want = std::min<int64_t>(want, std::min<int64_t>(kMaxF64Splits, k / 128));
+  want = std::min<int64_t>(want, std::min<int64_t>(kMaxF64Splits, k / kmin));
   if (want <= 1) return 1;
   *kchunk = (int)(((k + want - 1) / want + F64_BK - 1) / F64_BK) * F64_BK;
   return (k + *kchunk - 1) / *kchunk;
@@ -389,7 +392,7 @@ int f64_splits(int m, int n, int k, int batch, int* kchunk) {
 
 int gemm_f64_split_count(int m, int n, int k) {
   int kchunk = k;
-  return f64_splits(m, n, std::max(k, 0), 1, &kchunk);
+  return f64_splits(m, n, std::max(k, 0), 1, &kchunk, 128);
 }
 
 int gemm_f64_partials(Ctx& c, int m, int n, int k, const double* A, int64_t lda, int ta,
@@ -397,7 +400,7 @@ int gemm_f64_partials(Ctx& c, int m, int n, int k, const double* A, int64_t lda,
   if (m <= 0 || n <= 0) return 0;
   if (k < 0) k = 0;
   int kchunk = k;
-  const int splits = f64_splits(m, n, k, 1, &kchunk);
+  const int splits = f64_splits(m, n, k, 1, &kchunk, 128);
   if (c.dry) return splits;
   const int tm = (m + F64_BM - 1) / F64_BM, tn = (n + F64_BN - 1) / F64_BN;
   ProfScope ps(c, K_GEMM_F64, 2.0 * m * n * (double)k,

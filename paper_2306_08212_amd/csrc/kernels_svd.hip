@@ -1021,8 +1021,8 @@ __device__ __forceinline__ int chol_factor(int nb, int c0, const double* __restr
 // U[:, c0 : c0 + nb] <- U[:, c0 : c0 + nb] R^{-1} (row-major, ld kk) when the
 // block is healthy, in one launch.  G comes as the splits K slabs of its
 // product (gemm_f64_partials; one slab: G itself), which the workgroup sums
-// in slab order from 0.0 into LDS, the order of gemm()'s own sum, so G is
-// bitwise the one gemm() returns.  Each workgroup takes 64 rows of U; its
+// in slab order from 0.0 into LDS (the order the split-K sum kernel takes).
+// Each workgroup takes 64 rows of U; its
 // first wave factors G (every workgroup the same arithmetic on the same G,
 // so the same R^{-1} and verdict; the first workgroup records them), which
 // costs no time over one factorisation and saves a launch and a round trip
