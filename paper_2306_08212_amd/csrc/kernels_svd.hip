@@ -1028,12 +1028,8 @@ __device__ __forceinline__ int chol_factor(int nb, int c0, const double* __restr
 // costs no time over one factorisation and saves a launch and a round trip
 // of R^{-1} through memory.  While the first wave factors, the other three
 // stage the workgroup's rows of the block in LDS.  Apply: the rows
-// (transposed) sit in LDS next to
-// R^{-1}, and each thread forms a 4 x 4 tile of the product, wave w the
-// columns 16 w .. 16 w + 15, so a step over the inner index reads four
-// 16-byte LDS words for sixteen FMAs.  R^{-1} is upper triangular, so a wave
-// stops at its last column; the products are summed in increasing inner
-// index, one accumulator per element.
+// (transposed) sit in LDS next to R^{-1}, and the four waves form the 64 x 64
+// product on the FP64 matrix cores.
 // The nfb workgroups after the (m + 63) / 64 of the apply run the first
 // level of the Gram-Schmidt fallback instead, chunk blockIdx.x - (m + 63) /
 // 64 each, when the block is not healthy (tsqr_local_chunk, arguments q0,
@@ -1134,34 +1130,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     return;
   }
   if (!good) return;
+  // the product on the FP64 matrix cores: wave w forms the 32 x 32 quadrant
+  // (w / 2, w % 2) of the 64 x 64 result as 2 x 2 tiles of 16 x 16, over the
+  // 64 inner indices in steps of 4 (R^{-1} and the rows are zero beyond nb)
   const int w = t >> 6, lane = t & 63;
-  const int rb = (lane >> 2) * 4, cb = w * 16 + (lane & 3) * 4;
-  const int amax = min(nb, w * 16 + 16);   // R^{-1}[a][c] = 0 for a > c
-  double acc[4][4];
+  const int rq = (w >> 1) * 32, cq = (w & 1) * 32;
+  d4 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int a = 0; a < amax; ++a) {
-    const double2 p01 = *reinterpret_cast<const double2*>(&Pt[a][rb]);
-    const double2 p23 = *reinterpret_cast<const double2*>(&Pt[a][rb + 2]);
-    const double2 r01 = *reinterpret_cast<const double2*>(&Rs[a][cb]);
-    const double2 r23 = *reinterpret_cast<const double2*>(&Rs[a][cb + 2]);
-    const double p[4] = {p01.x, p01.y, p23.x, p23.y};
-    const double rr[4] = {r01.x, r01.y, r23.x, r23.y};
+    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = fma(p[i], rr[j], acc[i][j]);
+  for (int k0 = 0; k0 < OBW; k0 += 4) {
+    const int kr = k0 + (lane >> 4);
+    const double a0 = Pt[kr][rq + (lane & 15)], a1 = Pt[kr][rq + 16 + (lane & 15)];
+    const double b0 = Rs[kr][cq + (lane & 15)], b1 = Rs[kr][cq + 16 + (lane & 15)];
+    acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
   }
+  // result lane l, element q: row l / 16 + 4 q, column l % 16 of its tile
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int row = i0 + rb + i;
-    if (row >= m) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      if (cb + j < nb) U[(int64_t)row * kk + c0 + cb + j] = acc[i][j];
-  }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = i0 + rq + 16 * i + (lane >> 4) + 4 * q;
+        const int col = cq + 16 * j + (lane & 15);
+        if (row < m && col < nb) U[(int64_t)row * kk + c0 + col] = acc[i][j][q];
+      }
 }
 
 // In-place sign fix of the kk columns of row-major U (m x kk): the lowest
