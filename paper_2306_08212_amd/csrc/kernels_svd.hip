@@ -507,35 +507,35 @@ __global__ __launch_bounds__(256) void jac_colnorm_kernel(const double* __restri
 // A NaN ranks below every number (as -inf, ties by index), so the ranks are
 // always a permutation of 0..c-1 and order[] holds valid column indices
 // whatever the data: the indices feed gathers.
+// A workgroup ranks 64 keys; its four waves each count, for every one of
+// them, the keys of one quarter of the list that precede it.  Launch with
+// (c + 63) / 64 workgroups.
 __global__ __launch_bounds__(256) void jac_rank_kernel(const double* __restrict__ sig, int c, int kk,
                                                        int* __restrict__ order) {
-  // the keys pass through LDS 1024 at a time; each thread counts the keys
-  // that precede its own
-  __shared__ double ks[1024];
-  const int j = blockIdx.x * 256 + threadIdx.x;
+  __shared__ int part[4][64];
+  const int jl = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + jl;
   auto key = [](double x) { return x == x ? x : -INFINITY; };
   const double v = j < c ? key(sig[j]) : 0.0;
-  int rank = 0;
-  for (int i0 = 0; i0 < c; i0 += 1024) {
-    const int n = min(1024, c - i0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < n; e += 256) ks[e] = key(sig[i0 + e]);
-    __syncthreads();
-    int r4[4] = {0, 0, 0, 0};
-    int e = 0;
-    for (; e + 4 <= n; e += 4)
+  const int per = (c + 3) / 4, lo = q * per, hi = min(c, lo + per);
+  int r4[4] = {0, 0, 0, 0};
+  int i = lo;
+  for (; i + 4 <= hi; i += 4)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double w = ks[e + u];
-        r4[u] += (w > v) || (w == v && i0 + e + u < j);
-      }
-    for (; e < n; ++e) {
-      const double w = ks[e];
-      r4[0] += (w > v) || (w == v && i0 + e < j);
+    for (int u = 0; u < 4; ++u) {
+      const double w = key(sig[i + u]);
+      r4[u] += (w > v) || (w == v && i + u < j);
     }
-    rank += (r4[0] + r4[1]) + (r4[2] + r4[3]);
+  for (; i < hi; ++i) {
+    const double w = key(sig[i]);
+    r4[0] += (w > v) || (w == v && i < j);
   }
-  if (j < c && rank < kk) order[rank] = j;
+  part[q][jl] = (r4[0] + r4[1]) + (r4[2] + r4[3]);
+  __syncthreads();
+  if (q == 0 && j < c) {
+    const int rank = (part[0][jl] + part[1][jl]) + (part[2][jl] + part[3][jl]);
+    if (rank < kk) order[rank] = j;
+  }
 }
 
 // Uj[:, t] (row-major vr x kk) = column order[t] of the accumulated
@@ -1384,7 +1384,7 @@ void orth_sorted(Ctx& c, const double* A, int m, int n, double* Q) {
                        m, n, rows, part);
     hipLaunchKernelGGL(rm_colnorm_kernel, dim3((n + 255) / 256), dim3(256), 0, c.stream, part,
                        chunks, n, sig);
-    hipLaunchKernelGGL(jac_rank_kernel, dim3((n + 255) / 256), dim3(256), 0, c.stream, sig, n, n,
+    hipLaunchKernelGGL(jac_rank_kernel, dim3((n + 63) / 64), dim3(256), 0, c.stream, sig, n, n,
                        order);
     hipLaunchKernelGGL(gather_cols_kernel, dim3(grid_for((int64_t)m * n, 8192)), dim3(256), 0,
                        c.stream, A, m, n, order, Q);
@@ -1492,7 +1492,7 @@ void tsvd_core(Ctx& c, const double* M, int m, int n, int k, double tau, double*
     }
     ProfScope ps(c, K_SVD_OTHER, 0.0, 8.0 * (double)r * cp + 16.0 * (double)n * kk);
     hipLaunchKernelGGL(jac_colnorm_kernel, dim3(cp), dim3(256), 0, c.stream, X, r, cp, sig);
-    hipLaunchKernelGGL(jac_rank_kernel, dim3((cp + 255) / 256), dim3(256), 0, c.stream, sig, cp,
+    hipLaunchKernelGGL(jac_rank_kernel, dim3((cp + 63) / 64), dim3(256), 0, c.stream, sig, cp,
                        kk, order);
     hipLaunchKernelGGL(jac_pick_kernel, dim3(grid_for((int64_t)n * kk, 4096)), dim3(256), 0,
                        c.stream, V, n, cp, sig, order, kk, tau, Uj, S);
