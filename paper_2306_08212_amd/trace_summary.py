@@ -28,11 +28,12 @@ import sys
 
 
 def _name(row):
+    """The kernel's bare name (the trace holds it truncated with -T, or
+    demangled in full)."""
     n = row.get("Kernel_Name") or ""
-    n = n.split("(")[0]
     for pre in ("void ", "ctm::(anonymous namespace)::", "ctm::"):
         n = n.replace(pre, "")
-    return n.split("<")[0].strip()
+    return n.split("(")[0].split("<")[0].strip()
 
 
 def load(d):
