@@ -735,22 +735,38 @@ __device__ __forceinline__ void tsqr_apply_chunk(const double* __restrict__ Q, i
       Qs[rr][cc] = (i0 + rr < rows) ? Q[(int64_t)(i0 + rr) * OBW + cc] : 0.0;
     }
     __syncthreads();
-    // thread: column cc = t % 64 of rows t / 64 + 4 q (independent sums)
-    const int cc = t & 63, r0 = t >> 6;
-    double acc[TH / 4];
+    // on the FP64 matrix cores: wave w forms rows 32 w .. 32 w + 31 of the
+    // half, all 64 columns, as 2 x 4 tiles of 16 x 16 (result lane l,
+    // element q: row l / 16 + 4 q, column l % 16 of its tile)
+    const int lane = t & 63, rw = (t >> 6) * 32;
+    d4 acc[2][4];
 #pragma unroll
-    for (int q = 0; q < TH / 4; ++q) acc[q] = 0.0;
-    for (int a2 = 0; a2 < OBW; ++a2) {
-      const double wv = Ws[a2][cc];
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int q = 0; q < TH / 4; ++q) acc[q] += Qs[r0 + 4 * q][a2] * wv;
+      for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k0 = 0; k0 < OBW; k0 += 4) {
+      const int kr = k0 + (lane >> 4);
+      double av[2], bv[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) av[i] = Qs[rw + 16 * i + (lane & 15)][kr];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bv[j] = Ws[kr][16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[i], bv[j], acc[i][j], 0, 0, 0);
     }
-    if (cc < nb)
 #pragma unroll
-      for (int q = 0; q < TH / 4; ++q) {
-        const int rr = r0 + 4 * q;
-        if (i0 + rr < rows) dst[(int64_t)(i0 + rr) * ldd + cc] = acc[q];
-      }
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = rw + 16 * i + (lane >> 4) + 4 * q, cc = 16 * j + (lane & 15);
+          if (cc < nb && i0 + rr < rows) dst[(int64_t)(i0 + rr) * ldd + cc] = acc[i][j][q];
+        }
     __syncthreads();
   }
 }
