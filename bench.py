@@ -255,8 +255,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not "
-              f"supported (environment solves shard across GPUs by request, see DESIGN.md)",
+        print(f"bench.py: the benchmark runs on one GPU only; --gpus {args.gpus} is not "
+              f"supported (independent environment solves would shard across GPUs by request)",
               file=sys.stderr)
         sys.exit(2)
 

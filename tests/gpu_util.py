@@ -79,13 +79,12 @@ def permute(x, perm, dt_in, dt_out, scale=1.0):
 
 
 def log(*a):
-    """Print a test's measurement; on the GPU machine (GRAFT_REPO_ROOT set) also
-    append it to gpurun_out/test_log.txt, so passing tests leave their
-    numbers behind."""
+    """Print a test's measurement; with CTM_TEST_LOG naming a file, also
+    append it there, so passing tests leave their numbers behind."""
     print(*a, flush=True)
     sys.stdout.flush()
     import os
-    root = os.environ.get("GRAFT_REPO_ROOT")
-    if root and os.path.isdir(os.path.join(root, "gpurun_out")):
-        with open(os.path.join(root, "gpurun_out", "test_log.txt"), "a") as f:
+    path = os.environ.get("CTM_TEST_LOG")
+    if path and os.path.isdir(os.path.dirname(os.path.abspath(path))):
+        with open(path, "a") as f:
             f.write(" ".join(str(x) for x in a) + "\n")
