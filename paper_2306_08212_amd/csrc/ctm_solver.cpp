@@ -155,7 +155,9 @@ void run_branches(ctm_solver* s, const std::vector<std::function<void(Ctx&)>>& f
     c.arena.release(mk);
     return;
   }
-  const bool par = s->ev_fork != nullptr;
+  // CTM_DEBUG_SERIAL_BRANCHES runs the branches one after the other on the
+  // solver's stream (determinism diagnostics)
+  const bool par = s->ev_fork != nullptr && !std::getenv("CTM_DEBUG_SERIAL_BRANCHES");
   if (par) c.check(hipEventRecord(s->ev_fork, c.stream));
   std::vector<Ctx> ks(n);
   for (int b = 0; b < n; ++b) {
