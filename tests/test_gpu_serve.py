@@ -161,6 +161,33 @@ def test_no_write_past_the_workspace(D, chi, prec, method):
     assert bad == 0
 
 
+@pytest.mark.parametrize("D,chi,prec", [(3, 31, 1), (4, 40, 1), (5, 43, 1)])
+def test_results_do_not_depend_on_memory_around_the_workspace(D, chi, prec):
+    """The same solve, on a zero-filled workspace with 4 MiB before and after
+    it holding zeros in one run and NaN bit patterns in the other, gives
+    bitwise the same energies: no kernel reads memory outside the workspace
+    (a solve in the serving mix sits next to other solves' memory)."""
+    import torch
+    import paper_2306_08212_amd as P
+    A, B = site_tensors(2, D, 4)
+    cfg = P.Config(d=2, D=D, chi=chi, method=P.REDUCED, precision=prec)
+    n = P.workspace_size(cfg)
+    g = 1 << 22
+    out = []
+    for around in (0x00, 0xFF):
+        buf = torch.full((g + n + g,), around, dtype=torch.uint8, device="cuda")
+        buf[g:g + n].zero_()
+        torch.cuda.synchronize()
+        s = P.Solver(cfg, A, B, workspace=buf[g:g + n])
+        s.iterate(2)
+        e, eb = s.energy()
+        s.close()
+        torch.cuda.synchronize()
+        log(f"D={D} chi={chi} prec={prec} memory around the workspace {around:#x}: {e!r}")
+        out.append((e, eb))
+    assert out[0] == out[1]
+
+
 @pytest.mark.parametrize("D,chi,prec,method", [(3, 31, 1, 1), (6, 120, 1, 1), (8, 65, 1, 1),
                                                (4, 40, 0, 2), (3, 17, 2, 0), (5, 43, 1, 1),
                                                (8, 184, 1, 1), (7, 93, 1, 1), (7, 184, 1, 1)])
